@@ -1,0 +1,574 @@
+/*
+ * ixoracle.c -- plain, sequential CPU oracle for the filter-partition path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, calls or
+ * includes this file; only the test-suite, the smoke check and the CPU-baseline
+ * leg of the benchmark load it.  It shares no header, helper, table or
+ * constant with the HIP implementation.
+ *
+ * Every routine is written as the paper states the computation, one step at a
+ * time, in the paper's order and notation, with no blocking, fusion or
+ * reordering:
+ *   - map / inclusive scan / scatter semantics: Section 2.1 (combinator types
+ *     and the imperative meaning of scatter);
+ *   - partition2, sgmSum, mkSgmDescr, mkII: Section 2.1, figure "Running
+ *     Examples";
+ *   - partition2L (segmented partition): Section 6, "Segmented operations";
+ *   - the properties Range, Monotonic, Inj, Bij, FiltPart / InvFiltPart:
+ *     Section 2.3, figure "Array Properties" and the prose after it.
+ * Readings taken where the paper is ambiguous are listed beside the code that
+ * takes them.  Integer work only, except the f32 predicate x < s, which is a
+ * single IEEE single-precision comparison (the paper's benchmark arrays are
+ * f32, Section 6).
+ *
+ * Return value convention: 0 on success, -1 on invalid arguments,
+ * -2 on allocation failure.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+enum { IXO_I32 = 0, IXO_I64 = 1, IXO_F32 = 2 };
+enum { IXO_PRED_MOD_EQ = 0, IXO_PRED_LT = 1, IXO_PRED_FLAGS = 2 };
+enum { IXO_MODE_PARTITION = 0, IXO_MODE_FILTER = 1 };
+enum { IXO_MONO_LE = 0, IXO_MONO_LT = 1, IXO_MONO_GE = 2, IXO_MONO_GT = 3 };
+
+/* ------------------------------------------------------------------------ */
+/* The predicate p, applied by `map (\x -> p x) xs` (Section 2.1).          */
+/* MOD_EQ: floor-modulus of an integer key by d equals r (d > 0).  The paper */
+/* does not fix the sign convention of %; floor-mod (result in [0,d)) is    */
+/* the reading taken.  LT: f32 key < s, IEEE comparison (NaN gives false).  */
+/* FLAGS: a caller-supplied boolean array (partition2L's csL input).        */
+/* ------------------------------------------------------------------------ */
+static int64_t floor_mod(int64_t a, int64_t d) {
+    int64_t r = a % d;
+    if (r < 0) r += d;
+    return r;
+}
+
+static int valid_key_t(int key_t) {
+    return key_t == IXO_I32 || key_t == IXO_I64 || key_t == IXO_F32;
+}
+
+static int64_t key_bytes(int key_t) { return key_t == IXO_I64 ? 8 : 4; }
+
+int ixo_map_pred(const void *xs, int key_t, int64_t n, int pred_kind,
+                 int64_t d, int64_t r, float s, const uint8_t *flags_in,
+                 uint8_t *cs) {
+    if (n < 0 || (n > 0 && !cs)) return -1;
+    if (pred_kind == IXO_PRED_MOD_EQ) {
+        if (d <= 0 || (n > 0 && !xs)) return -1;
+        if (key_t != IXO_I32 && key_t != IXO_I64) return -1;
+        for (int64_t i = 0; i < n; i++) {
+            int64_t x = key_t == IXO_I32 ? (int64_t)((const int32_t *)xs)[i]
+                                         : ((const int64_t *)xs)[i];
+            cs[i] = floor_mod(x, d) == r;
+        }
+    } else if (pred_kind == IXO_PRED_LT) {
+        if (key_t != IXO_F32 || (n > 0 && !xs)) return -1;
+        for (int64_t i = 0; i < n; i++) {
+            float x = ((const float *)xs)[i];
+            cs[i] = x < s;
+        }
+    } else if (pred_kind == IXO_PRED_FLAGS) {
+        if (n > 0 && !flags_in) return -1;
+        for (int64_t i = 0; i < n; i++) cs[i] = flags_in[i] != 0;
+    } else {
+        return -1;
+    }
+    return 0;
+}
+
+/* scan (+) 0 xs -- inclusive prefix sum (Section 2.1). */
+static void scan_plus_i64(const int64_t *xs, int64_t n, int64_t *out) {
+    int64_t acc = 0;
+    for (int64_t i = 0; i < n; i++) {
+        acc = acc + xs[i];
+        out[i] = acc;
+    }
+}
+
+/* scatter dst is vs: for i in 0..m-1, if 0 <= is[i] < len(dst) then
+ * dst[is[i]] := vs[i] (Section 2.1).  The printed bound says "< m", but the
+ * type gives dst length n and the prose says "out of bounds in dst"; the bound
+ * taken is the length of dst.  Elements are moved as raw bytes. */
+int ixo_scatter(void *dst, int64_t n_dst, const int64_t *is, const void *vs,
+                int64_t m, int64_t elem_bytes) {
+    if (n_dst < 0 || m < 0 || elem_bytes <= 0) return -1;
+    if (m > 0 && (!is || !vs)) return -1;
+    for (int64_t i = 0; i < m; i++) {
+        if (0 <= is[i] && is[i] < n_dst)
+            memcpy((char *)dst + is[i] * elem_bytes,
+                   (const char *)vs + i * elem_bytes, (size_t)elem_bytes);
+    }
+    return 0;
+}
+
+/* Gather: dst[i] := src[is[i]] (array indexing x[i], Section 2.1).  Every
+ * index must lie in [0, n_src): returns -1 before writing anything otherwise. */
+int ixo_gather(void *dst, const void *src, int64_t n_src, const int64_t *is,
+               int64_t m, int64_t elem_bytes) {
+    if (n_src < 0 || m < 0 || elem_bytes <= 0) return -1;
+    for (int64_t i = 0; i < m; i++)
+        if (is[i] < 0 || is[i] >= n_src) return -1;
+    for (int64_t i = 0; i < m; i++)
+        memcpy((char *)dst + i * elem_bytes,
+               (const char *)src + is[i] * elem_bytes, (size_t)elem_bytes);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* partition2 (Section 2.1, figure "Running Examples", left):               */
+/*   cs       = map p xs                                                    */
+/*   flagsT   = map (c -> c ? 1 : 0) cs                                     */
+/*   flagsF   = map (b -> 1 - b) flagsT                                     */
+/*   indicesT = scan (+) 0 flagsT                                           */
+/*   num_true = n > 0 ? indicesT[n-1] : 0                                   */
+/*   tmp      = scan (+) 0 flagsF                                           */
+/*   indicesF = map (t -> t + num_true) tmp                                 */
+/*   indices  = map3 (c t f -> c ? t-1 : f-1) cs indicesT indicesF          */
+/*   ys       = scatter (replicate n 0) indices xs                          */
+/* returns (num_true, ys).  `indices` is also returned: it is the scatter   */
+/* array whose InvFiltPart property the paper proves.                       */
+/*                                                                          */
+/* FILTER mode is the paper's `filter` (FiltPart with p^f = p and no        */
+/* partitioning predicate): indices = c ? t-1 : -1, and the scatter target  */
+/* has length num_true; the -1 entries are out of bounds and ignored.       */
+/* ------------------------------------------------------------------------ */
+static int partition2_from_cs(const void *xs, int64_t kb, int64_t n,
+                              const uint8_t *cs, int mode, void *ys,
+                              int64_t *indices_out, int64_t *num_true_out) {
+    int64_t *flagsT = NULL, *flagsF = NULL, *indicesT = NULL, *tmp = NULL,
+            *indicesF = NULL, *indices = NULL;
+    int rc = -2;
+    size_t nb = (size_t)(n > 0 ? n : 1) * sizeof(int64_t);
+    flagsT = malloc(nb);
+    indicesT = malloc(nb);
+    indices = indices_out ? indices_out : malloc(nb);
+    if (!flagsT || !indicesT || !indices) goto done;
+
+    for (int64_t i = 0; i < n; i++) flagsT[i] = cs[i] ? 1 : 0;
+    scan_plus_i64(flagsT, n, indicesT);
+    int64_t num_true = n > 0 ? indicesT[n - 1] : 0;
+
+    if (mode == IXO_MODE_PARTITION) {
+        flagsF = malloc(nb);
+        tmp = malloc(nb);
+        if (!flagsF || !tmp) goto done;
+        for (int64_t i = 0; i < n; i++) flagsF[i] = 1 - flagsT[i];
+        scan_plus_i64(flagsF, n, tmp);
+        free(flagsF); flagsF = NULL;
+        indicesF = tmp; /* indicesF = map (t -> t + num_true) tmp, in place */
+        tmp = NULL;
+        for (int64_t i = 0; i < n; i++) indicesF[i] = indicesF[i] + num_true;
+        for (int64_t i = 0; i < n; i++)
+            indices[i] = cs[i] ? indicesT[i] - 1 : indicesF[i] - 1;
+        if (ys) {
+            memset(ys, 0, (size_t)(n * kb)); /* replicate n 0 */
+            ixo_scatter(ys, n, indices, xs, n, kb);
+        }
+    } else {
+        for (int64_t i = 0; i < n; i++)
+            indices[i] = cs[i] ? indicesT[i] - 1 : -1;
+        if (ys) {
+            memset(ys, 0, (size_t)(num_true * kb)); /* replicate num_true 0 */
+            ixo_scatter(ys, num_true, indices, xs, n, kb);
+        }
+    }
+    if (num_true_out) *num_true_out = num_true;
+    rc = 0;
+done:
+    free(flagsT); free(flagsF); free(indicesT); free(tmp); free(indicesF);
+    if (indices != indices_out) free(indices);
+    return rc;
+}
+
+int ixo_partition2(const void *xs, int key_t, int64_t n, int pred_kind,
+                   int64_t d, int64_t r, float s, const uint8_t *flags_in,
+                   int mode, void *ys, int64_t *indices, int64_t *num_true) {
+    if (n < 0 || !valid_key_t(key_t)) return -1;
+    if (mode != IXO_MODE_PARTITION && mode != IXO_MODE_FILTER) return -1;
+    uint8_t *cs = malloc((size_t)(n > 0 ? n : 1));
+    if (!cs) return -2;
+    int rc = ixo_map_pred(xs, key_t, n, pred_kind, d, r, s, flags_in, cs);
+    if (rc == 0)
+        rc = partition2_from_cs(xs, key_bytes(key_t), n, cs, mode, ys,
+                                indices, num_true);
+    free(cs);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Segmented helpers (Section 2.1, figure "Running Examples", right).       */
+/* ------------------------------------------------------------------------ */
+
+/* sgmSum flags xs: inclusive scan with the lifted operator
+ *   (fx, vx) (+) (fy, vy) = (fx || fy, fy ? vy : vx + vy),  neutral (false, 0).
+ * The printed lambda binds f1 v1 f2 v2 but its body uses fx fy vx vy; the
+ * operator above is the reading taken (the standard segmented-scan lift). */
+int ixo_sgm_sum(const uint8_t *flags, const int64_t *xs, int64_t n,
+                int64_t *out) {
+    if (n < 0) return -1;
+    int acc_f = 0;
+    int64_t acc_v = 0;
+    for (int64_t i = 0; i < n; i++) {
+        int fy = flags[i] != 0;
+        int64_t vy = xs[i];
+        int f = acc_f || fy;
+        int64_t v = fy ? vy : acc_v + vy;
+        acc_f = f;
+        acc_v = v;
+        out[i] = acc_v;
+    }
+    return 0;
+}
+
+/* mkSgmDescr shape xs: flat array of length sum(shape) in which every
+ * non-empty segment starts with xs[k] and is otherwise zero.  Steps:
+ *   rot = map (i -> i == 0 ? 0 : shape[i-1]) (iota m)
+ *   scn = scan (+) 0 rot                       (segment offsets)
+ *   ind = map2 (s i -> s <= 0 ? -1 : i) shape scn
+ *   len = m > 0 ? scn[m-1] + shape[m-1] : 0
+ *   res = scatter (replicate len 0) ind xs
+ * Empty segments scatter to -1, which scatter ignores.  `out` must hold
+ * sum(shape) entries; returns -1 if a size is negative. */
+int ixo_mk_sgm_descr(const int64_t *shape, int64_t m, const int64_t *xs,
+                     int64_t *out, int64_t out_len) {
+    if (m < 0) return -1;
+    for (int64_t k = 0; k < m; k++)
+        if (shape[k] < 0) return -1;
+    int64_t *rot = malloc((size_t)(m > 0 ? m : 1) * sizeof(int64_t));
+    int64_t *scn = malloc((size_t)(m > 0 ? m : 1) * sizeof(int64_t));
+    int64_t *ind = malloc((size_t)(m > 0 ? m : 1) * sizeof(int64_t));
+    if (!rot || !scn || !ind) { free(rot); free(scn); free(ind); return -2; }
+    for (int64_t i = 0; i < m; i++) rot[i] = i == 0 ? 0 : shape[i - 1];
+    scan_plus_i64(rot, m, scn);
+    for (int64_t k = 0; k < m; k++) ind[k] = shape[k] <= 0 ? -1 : scn[k];
+    int64_t len = m > 0 ? scn[m - 1] + shape[m - 1] : 0;
+    int rc = -1;
+    if (len == out_len) {
+        for (int64_t j = 0; j < len; j++) out[j] = 0;
+        rc = ixo_scatter(out, len, ind, xs, m, (int64_t)sizeof(int64_t));
+    }
+    free(rot); free(scn); free(ind);
+    return rc;
+}
+
+/* mkII shape: segment number of every flat element.  Steps:
+ *   beg_vs  = map (i -> i + 1) (iota m)
+ *   sct_vs1 = mkSgmDescr shape beg_vs
+ *   sct_vs  = map (v -> v == 0 ? 0 : v - 1) sct_vs1
+ *   flags   = map (f -> f > 0) sct_vs
+ *   II      = sgmSum flags sct_vs
+ * (The listing mixes the names sct_vs / scat_vs; one array is meant.)  The
+ * worked example maps [0,2,1,0,3] to [1,1,2,4,4,4]. */
+int ixo_mk_ii(const int64_t *shape, int64_t m, int64_t *out, int64_t out_len) {
+    if (m < 0) return -1;
+    int64_t *beg_vs = malloc((size_t)(m > 0 ? m : 1) * sizeof(int64_t));
+    int64_t *sct = malloc((size_t)(out_len > 0 ? out_len : 1) * sizeof(int64_t));
+    uint8_t *flags = malloc((size_t)(out_len > 0 ? out_len : 1));
+    int rc = -2;
+    if (!beg_vs || !sct || !flags) goto done;
+    for (int64_t i = 0; i < m; i++) beg_vs[i] = i + 1;
+    rc = ixo_mk_sgm_descr(shape, m, beg_vs, sct, out_len);
+    if (rc != 0) goto done;
+    for (int64_t j = 0; j < out_len; j++) sct[j] = sct[j] == 0 ? 0 : sct[j] - 1;
+    /* flags = map (f -> f > 0) sct_vs, as printed.  Segment 0's start value
+     * is 0 after the decrement, so its start is not flagged; the scan still
+     * yields 0 there because every value before it is 0. */
+    for (int64_t j = 0; j < out_len; j++) flags[j] = sct[j] > 0;
+    rc = ixo_sgm_sum(flags, sct, out_len, out);
+done:
+    free(beg_vs); free(sct); free(flags);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* partition2L -- partition2 applied to every row of a jagged array given by */
+/* its shape (Section 6, "Segmented operations").  Row k occupies the flat  */
+/* interval [o_k, o_k + shape[k]) with o_k = sum of the earlier sizes; rows  */
+/* may be empty.  Each row is partitioned on its own, and its scatter        */
+/* indices are shifted by the row offset, so trues of row k land at          */
+/* o_k + (#trues before i in the row) and falses at o_k + T_k + (#falses     */
+/* before i in the row), T_k = number of trues in row k.  In FILTER mode the */
+/* kept elements of row k are packed at o'_k = sum of the earlier rows'      */
+/* kept counts (filter_seg) and dropped elements get index -1.               */
+/* The descriptor flag array is mkSgmDescr shape (replicate m 1), written as */
+/* bytes (1 at the start of every non-empty row, 0 elsewhere).              */
+/* ------------------------------------------------------------------------ */
+int ixo_partition2L(const void *xs, int key_t, int64_t n, const int64_t *shape,
+                    int64_t m, int pred_kind, int64_t d, int64_t r, float s,
+                    const uint8_t *flags_in, int mode, void *ys,
+                    int64_t *indices, int64_t *seg_split, uint8_t *flags_out) {
+    if (n < 0 || m < 0 || !valid_key_t(key_t)) return -1;
+    if (mode != IXO_MODE_PARTITION && mode != IXO_MODE_FILTER) return -1;
+    int64_t total = 0;
+    for (int64_t k = 0; k < m; k++) {
+        if (shape[k] < 0) return -1;
+        total += shape[k];
+    }
+    if (total != n) return -1;
+    int64_t kb = key_bytes(key_t);
+    uint8_t *cs = malloc((size_t)(n > 0 ? n : 1));
+    if (!cs) return -2;
+    int rc = ixo_map_pred(xs, key_t, n, pred_kind, d, r, s, flags_in, cs);
+    if (rc != 0) { free(cs); return rc; }
+
+    int64_t o = 0, okept = 0;
+    for (int64_t k = 0; k < m && rc == 0; k++) {
+        int64_t sk = shape[k];
+        int64_t tk = 0;
+        int64_t *loc = malloc((size_t)(sk > 0 ? sk : 1) * sizeof(int64_t));
+        if (!loc) { rc = -2; break; }
+        rc = partition2_from_cs((const char *)xs + o * kb, kb, sk, cs + o, mode,
+                                NULL, loc, &tk);
+        if (rc == 0) {
+            int64_t base = mode == IXO_MODE_PARTITION ? o : okept;
+            for (int64_t i = 0; i < sk; i++) {
+                int64_t g = loc[i] < 0 ? -1 : base + loc[i];
+                if (indices) indices[o + i] = g;
+            }
+            if (ys) {
+                /* scatter the row into its slice of the output */
+                int64_t len = mode == IXO_MODE_PARTITION ? sk : tk;
+                char *dst = (char *)ys + base * kb;
+                memset(dst, 0, (size_t)(len * kb));
+                ixo_scatter(dst, len, loc, (const char *)xs + o * kb, sk, kb);
+            }
+            if (seg_split) seg_split[k] = tk;
+        }
+        free(loc);
+        o += sk;
+        okept += tk;
+    }
+    if (rc == 0 && flags_out) {
+        int64_t *ones = malloc((size_t)(m > 0 ? m : 1) * sizeof(int64_t));
+        int64_t *descr = malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+        if (!ones || !descr) rc = -2;
+        else {
+            for (int64_t k = 0; k < m; k++) ones[k] = 1;
+            rc = ixo_mk_sgm_descr(shape, m, ones, descr, n);
+            for (int64_t j = 0; rc == 0 && j < n; j++)
+                flags_out[j] = (uint8_t)descr[j];
+        }
+        free(ones); free(descr);
+    }
+    free(cs);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Property checkers (Section 2.3, figure "Array Properties").              */
+/* Each writes a verdict {holds, first_violation, aux} as three int64:       */
+/* holds is 1 or 0; first_violation is -1 when the property holds.  The      */
+/* paper proves properties and never locates a failure, so the index         */
+/* conventions below are this library's definitions:                         */
+/*   Range [lo,hi): min i with X[i] outside [lo,hi); aux = X[i].             */
+/*     (The figure prints a closed interval, every use in the paper is       */
+/*      half-open; half-open is taken, with explicit bounds.)                */
+/*   Monotonic op: min i >= 1 with !(X[i-1] op X[i]) (the later element);    */
+/*     aux = 0.  (The printed bound j < n-1 would leave the last element     */
+/*     unconstrained; j < n is taken.  For a transitive op all-pairs and     */
+/*     adjacent pairs agree.)                                                */
+/*   Inj Rcd=[lo,hi): min i such that some j < i has X[j] = X[i] in Rcd      */
+/*     (the earliest second occurrence); aux = X[i].  Entries outside Rcd    */
+/*     are ignored.                                                          */
+/*   Bij Rcd=[lo,hi) Img=[ilo,ihi): Inj Rcd, every in-Rcd value lies in Img, */
+/*     and the number of in-Rcd entries equals |Img|.  first_violation = min */
+/*     of the Inj violation and the first in-Rcd value outside Img (aux =    */
+/*     that value); failing only on the count gives first_violation = n and  */
+/*     aux = the smallest value of Img that is not attained.                 */
+/* ------------------------------------------------------------------------ */
+static void verdict_set(int64_t *v, int holds, int64_t fv, int64_t aux) {
+    v[0] = holds;
+    v[1] = fv;
+    v[2] = aux;
+}
+
+int ixo_check_range(const int64_t *X, int64_t n, int64_t lo, int64_t hi,
+                    int64_t *v) {
+    if (n < 0) return -1;
+    for (int64_t i = 0; i < n; i++) {
+        if (!(lo <= X[i] && X[i] < hi)) {
+            verdict_set(v, 0, i, X[i]);
+            return 0;
+        }
+    }
+    verdict_set(v, 1, -1, 0);
+    return 0;
+}
+
+static int mono_ok(int64_t a, int64_t b, int op) {
+    switch (op) {
+    case IXO_MONO_LE: return a <= b;
+    case IXO_MONO_LT: return a < b;
+    case IXO_MONO_GE: return a >= b;
+    default: return a > b;
+    }
+}
+
+int ixo_check_mono(const int64_t *X, int64_t n, int op, int64_t *v) {
+    if (n < 0 || op < 0 || op > 3) return -1;
+    for (int64_t i = 1; i < n; i++) {
+        if (!mono_ok(X[i - 1], X[i], op)) {
+            verdict_set(v, 0, i, 0);
+            return 0;
+        }
+    }
+    verdict_set(v, 1, -1, 0);
+    return 0;
+}
+
+/* Seen-set over the restricted co-domain [lo,hi): one bit per value. */
+typedef struct {
+    uint8_t *bits;
+    int64_t lo;
+} seen_set;
+
+static int seen_init(seen_set *s, int64_t lo, int64_t hi) {
+    uint64_t width = (uint64_t)(hi - lo);
+    s->lo = lo;
+    s->bits = calloc((size_t)(width / 8 + 1), 1);
+    return s->bits ? 0 : -2;
+}
+static int seen_test_and_set(seen_set *s, int64_t x) {
+    uint64_t o = (uint64_t)(x - s->lo);
+    int was = (s->bits[o >> 3] >> (o & 7)) & 1;
+    s->bits[o >> 3] |= (uint8_t)(1u << (o & 7));
+    return was;
+}
+static int seen_test(const seen_set *s, int64_t x) {
+    uint64_t o = (uint64_t)(x - s->lo);
+    return (s->bits[o >> 3] >> (o & 7)) & 1;
+}
+
+/* The bitmap holds hi-lo bits; co-domains wider than 2^40 values are refused. */
+static int rcd_ok(int64_t lo, int64_t hi) {
+    return lo <= hi && (uint64_t)(hi - lo) <= ((uint64_t)1 << 40);
+}
+
+int ixo_check_inj(const int64_t *X, int64_t n, int64_t lo, int64_t hi,
+                  int64_t *v) {
+    if (n < 0 || !rcd_ok(lo, hi)) return -1;
+    seen_set s;
+    if (seen_init(&s, lo, hi)) return -2;
+    verdict_set(v, 1, -1, 0);
+    for (int64_t i = 0; i < n; i++) {
+        int64_t x = X[i];
+        if (lo <= x && x < hi && seen_test_and_set(&s, x)) {
+            verdict_set(v, 0, i, x);
+            break;
+        }
+    }
+    free(s.bits);
+    return 0;
+}
+
+int ixo_check_bij(const int64_t *X, int64_t n, int64_t lo, int64_t hi,
+                  int64_t ilo, int64_t ihi, int64_t *v) {
+    if (n < 0 || !rcd_ok(lo, hi) || ilo > ihi || ilo < lo || ihi > hi)
+        return -1;
+    seen_set s;
+    if (seen_init(&s, lo, hi)) return -2;
+    int64_t count = 0;
+    verdict_set(v, 1, -1, 0);
+    for (int64_t i = 0; i < n; i++) {
+        int64_t x = X[i];
+        if (!(lo <= x && x < hi)) continue;
+        count++;
+        if (seen_test_and_set(&s, x) || !(ilo <= x && x < ihi)) {
+            verdict_set(v, 0, i, x);
+            break;
+        }
+    }
+    if (v[0] == 1 && count != ihi - ilo) {
+        /* Injective and inside Img, yet fewer values than |Img|. */
+        int64_t miss = ilo;
+        while (miss < ihi && seen_test(&s, miss)) miss++;
+        verdict_set(v, 0, n, miss);
+    }
+    free(s.bits);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* FiltPart check on the outputs of a flat partition (Section 2.3: FiltPart */
+/* and InvFiltPart; partition2's postcondition, Section 2.1).                */
+/* Inputs: X (the partitioned keys), the predicate, Y (the output keys), Z   */
+/* (the scatter indices) and split.  Sub-checks, numbered as the bits of     */
+/* aux:                                                                      */
+/*   bit 0  Equiv: split == number of elements satisfying p^f-and-p^p        */
+/*          (PARTITION: the trues of p; FILTER: the kept elements);          */
+/*   bit 1  Bij: PARTITION -- Z restricted to [0,n) is a bijection onto      */
+/*          [0,n) (every Z[i] in [0,n), no repeats); FILTER -- kept Z[i] lie */
+/*          in [0,split) without repeats, dropped Z[i] lie outside [0,split);*/
+/*   bit 2  class order: PARTITION -- Z[i] < split exactly when p holds;     */
+/*   bit 3  stability: inside each class Z is strictly increasing in i       */
+/*          (InvFiltPart, item (3));                                         */
+/*   bit 4  values: Y[Z[i]] == X[i] bit for bit, for every i whose Z[i] is a */
+/*          valid position of Y.                                             */
+/* holds iff no bit is set; first_violation = the least index i at which an  */
+/* index-wise sub-check (bits 1-4) fails, n if only bit 0 fails, -1 if all   */
+/* hold.  aux = the set of failing bits over the whole array.                */
+/* ------------------------------------------------------------------------ */
+int ixo_check_filtpart(const void *X, int key_t, int64_t n, int pred_kind,
+                       int64_t d, int64_t r, float s, const uint8_t *flags_in,
+                       int mode, const void *Y, const int64_t *Z, int64_t split,
+                       int64_t *v) {
+    if (n < 0 || !valid_key_t(key_t)) return -1;
+    if (mode != IXO_MODE_PARTITION && mode != IXO_MODE_FILTER) return -1;
+    int64_t kb = key_bytes(key_t);
+    uint8_t *cs = malloc((size_t)(n > 0 ? n : 1));
+    if (!cs) return -2;
+    int rc = ixo_map_pred(X, key_t, n, pred_kind, d, r, s, flags_in, cs);
+    if (rc) { free(cs); return rc; }
+
+    int64_t ntrue = 0;
+    for (int64_t i = 0; i < n; i++) ntrue += cs[i];
+    int64_t aux = 0;
+    int64_t first = -1;
+    if (split != ntrue) aux |= 1;
+
+    int64_t ylen = mode == IXO_MODE_PARTITION ? n : split;
+    seen_set seen;
+    if (seen_init(&seen, 0, n > 0 ? n : 1)) { free(cs); return -2; }
+    int has_last[2] = {0, 0};
+    int64_t last[2] = {0, 0};
+    for (int64_t i = 0; i < n; i++) {
+        int64_t z = Z[i];
+        int c = cs[i];
+        int64_t bad = 0;
+        int kept = mode == IXO_MODE_PARTITION || c;
+        if (mode == IXO_MODE_PARTITION) {
+            if (!(0 <= z && z < n) || seen_test_and_set(&seen, z)) bad |= 2;
+            if ((z < split) != (c != 0)) bad |= 4;
+        } else {
+            if (c) {
+                if (!(0 <= z && z < split) || z >= n ||
+                    seen_test_and_set(&seen, z))
+                    bad |= 2;
+            } else if (0 <= z && z < split) {
+                bad |= 2;
+            }
+        }
+        if (kept) {
+            int cls = mode == IXO_MODE_PARTITION ? c : 1;
+            if (has_last[cls] && !(z > last[cls])) bad |= 8;
+            has_last[cls] = 1;
+            last[cls] = z;
+            if (0 <= z && z < ylen &&
+                memcmp((const char *)Y + z * kb, (const char *)X + i * kb,
+                       (size_t)kb) != 0)
+                bad |= 16;
+        }
+        if (bad) {
+            if (first < 0) first = i;
+            aux |= bad;
+        }
+    }
+    free(seen.bits);
+    free(cs);
+    if (aux == 0) verdict_set(v, 1, -1, 0);
+    else verdict_set(v, 0, first >= 0 ? first : n, aux);
+    return 0;
+}
