@@ -1,0 +1,263 @@
+/*
+ * ixpart.h -- C ABI of the MI355X (gfx950) filter-partition library.
+ *
+ * The library computes, on one AMD Instinct MI355X, the data-parallel programs
+ * whose index arrays the paper "Verifying Properties of Index Arrays in a
+ * Purely-Functional Data-Parallel Language" reasons about:
+ *   - partition2 (Section 2.1, figure "Running Examples"): a stable two-way
+ *     partition built from map (the predicate), scan (+) of the flags, an
+ *     index map and a scatter;
+ *   - filter (FiltPart with a filtering predicate, Section 2.3 and Section 6);
+ *   - partition2L / filter_seg (Section 6, "Segmented operations"): the same
+ *     applied to every row of a jagged array given by its shape, rows may be
+ *     empty;
+ *   - scatter (Section 2.1) restricted to injective index arrays, and its
+ *     inverse, a gather;
+ *   - run-time checkers of the array properties Range, Monotonic, Inj, Bij and
+ *     FiltPart (Section 2.3, figure "Array Properties").
+ *
+ * Conventions common to every entry point
+ *   - Pointers named d_* or documented as "device" are device pointers
+ *     (hipMalloc / torch CUDA tensors); the caller owns every buffer.  Other
+ *     pointers (ixp_pred, ixp_prop_args, ixp_tuning) are host pointers read
+ *     during the call only.
+ *   - Device buffers must be aligned to their element size.  Buffers aligned
+ *     to 16 bytes take the vector-load path; others are still correct.
+ *   - `stream` is a hipStream_t passed as void* (NULL = null stream).  Every
+ *     call only enqueues work on `stream`: no host synchronisation, no
+ *     allocation, no hipMemset -- except the functions documented as
+ *     "blocking" (autotuning, graph creation, error read-back).
+ *   - Argument errors are detected on the host before anything is enqueued and
+ *     reported as a negative status; a failed kernel launch returns IXP_EHIP.
+ *     No C++ exception crosses this interface.
+ *   - Workspaces: query the size, allocate device memory of at least that many
+ *     bytes, pass it in.  Its contents need no initialisation; a workspace may
+ *     not be shared by calls that can run concurrently.
+ */
+#ifndef IXPART_H
+#define IXPART_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------- */
+enum {
+    IXP_OK = 0,
+    IXP_EINVAL = -1,        /* bad argument: null pointer, negative size, ... */
+    IXP_ENOMEM = -2,        /* host allocation failed (graph objects only)    */
+    IXP_EHIP = -3,          /* a HIP runtime call or kernel launch failed     */
+    IXP_EUNSUPPORTED = -4,  /* valid request this build does not implement    */
+    IXP_EWORKSPACE = -5,    /* workspace missing or smaller than required     */
+    IXP_EDEVICE = -6        /* a kernel reported an error in the workspace    */
+};
+const char *ixp_status_str(int status);
+
+/* ---- element types, predicates, modes ------------------------------------ */
+enum { IXP_I32 = 0, IXP_I64 = 1, IXP_F32 = 2, IXP_U8 = 3 };
+
+/* The predicate p mapped over the keys (Section 2.1: cs = map p xs).
+ *   IXP_PRED_MOD_EQ: keys I32; p(x) = (x mod d == r) with the floor modulus
+ *                    (result in [0,d)); 1 <= d < 2^32.
+ *   IXP_PRED_LT:     keys F32; p(x) = (x < s), one IEEE single comparison,
+ *                    NaN gives false.
+ *   IXP_PRED_FLAGS:  keys I32 or F32 (moved as bits); p(i) = flags[i] != 0,
+ *                    `flags` a device u8 array of length n (partition2L's csL). */
+enum { IXP_PRED_MOD_EQ = 0, IXP_PRED_LT = 1, IXP_PRED_FLAGS = 2 };
+typedef struct {
+    int32_t kind;
+    int32_t reserved0;
+    int64_t d;
+    int64_t r;
+    float s;
+    int32_t reserved1;
+    const uint8_t *flags;   /* device */
+} ixp_pred;
+
+/* IXP_MODE_PARTITION: FiltPart with p^f = true and partition predicate p --
+ *   partition2: trues first, falses after, both in input order.
+ * IXP_MODE_FILTER: FiltPart with p^f = p and no partition -- filter: only the
+ *   trues are kept, in input order; dropped elements get index -1. */
+enum { IXP_MODE_PARTITION = 0, IXP_MODE_FILTER = 1 };
+
+/* ---- flat partition (partition2 / filter) -------------------------------- */
+
+/* Bytes of workspace ixp_partition needs for n elements. */
+size_t ixp_partition_workspace(int64_t n);
+
+/* Stable partition of keys[0..n) by `pred` (Section 2.1, partition2):
+ *   out_idx[i]  = destination of element i, the scatter index array whose
+ *                 InvFiltPart property the paper states:
+ *                   PARTITION: c_i ? #trues before i : T + #falses before i
+ *                   FILTER:    c_i ? #trues before i : -1
+ *   out_keys    = scatter of the keys by out_idx (length n in PARTITION mode,
+ *                 T in FILTER mode; positions >= T untouched in FILTER mode);
+ *   *d_split    = T, the number of trues (partition2's num_true), int64.
+ * key_t: IXP_I32 or IXP_F32 (see ixp_pred); idx_t: IXP_I32 (needs n < 2^31)
+ * or IXP_I64.  out_keys and out_idx may each be NULL (not produced); d_split
+ * is required.  n == 0 is valid and writes T = 0.
+ * Enqueues 2-3 kernels on `stream`; capturable into a HIP graph. */
+int ixp_partition(const void *keys, int32_t key_t, int64_t n,
+                  const ixp_pred *pred, int32_t mode, void *out_keys,
+                  void *out_idx, int32_t idx_t, int64_t *d_split, void *ws,
+                  size_t ws_bytes, void *stream);
+
+/* ---- segmented partition (partition2L / filter_seg) ----------------------- */
+
+/* Tile shape of the segmented kernels: `block` threads (256 or 512) each
+ * holding `rows` x 4 consecutive-by-quads elements (rows in {2,4,8}); a tile
+ * is block*rows*4 elements.  `wgs_per_cu` sizes the persistent grid (0 = 4).
+ * A NULL tuning pointer selects the library default. */
+typedef struct {
+    int32_t block;
+    int32_t rows;
+    int32_t wgs_per_cu;
+    int32_t reserved;
+} ixp_tuning;
+
+size_t ixp_segmented_workspace(int64_t n, int64_t m, const ixp_tuning *tune);
+
+/* partition2 applied to each row of a jagged array (Section 6, partition2L).
+ * d_shape: device int64[m], row sizes (>= 0, empty rows allowed, sum = n).
+ * Row k covers [o_k, o_k + shape[k]) with o_k the sum of the earlier sizes.
+ *   PARTITION: out_idx[i] = o_k + (c_i ? #trues before i in row k
+ *                                       : T_k + #falses before i in row k),
+ *              out_keys   = every row partitioned in place of the row;
+ *   FILTER:    kept elements of all rows packed row after row (filter_seg),
+ *              out_idx[i] = -1 for dropped elements.
+ *   d_seg_split[k] = T_k, the number of trues of row k (device int64[m]).
+ *   d_flags_out (nullable, device u8[n]) = the segment descriptor: 1 at the
+ *              first element of every non-empty row, 0 elsewhere (mkSgmDescr
+ *              applied to a row of ones, Section 2.1).
+ * A negative size or a size sum different from n is detected on the device:
+ * the call then writes no output and ixp_read_error() on the same workspace
+ * reports IXP_EINVAL.  One persistent kernel does all rows; 3 kernels total. */
+int ixp_segmented_partition(const void *keys, int32_t key_t, int64_t n,
+                            const int64_t *d_shape, int64_t m,
+                            const ixp_pred *pred, int32_t mode, void *out_keys,
+                            void *out_idx, int32_t idx_t, int64_t *d_seg_split,
+                            uint8_t *d_flags_out, const ixp_tuning *tune,
+                            void *ws, size_t ws_bytes, void *stream);
+
+/* Blocking: times every candidate tiling on the given arguments (which it
+ * overwrites) and stores the fastest in *best (and its time in *best_ms). */
+int ixp_tune_segmented(const void *keys, int32_t key_t, int64_t n,
+                       const int64_t *d_shape, int64_t m, const ixp_pred *pred,
+                       int32_t mode, void *out_keys, void *out_idx,
+                       int32_t idx_t, int64_t *d_seg_split,
+                       uint8_t *d_flags_out, void *ws, size_t ws_bytes,
+                       int32_t reps, ixp_tuning *best, float *best_ms,
+                       void *stream);
+
+/* HIP-graph form: blocking creation captures one ixp_segmented_partition call
+ * (all its kernels) into an instantiated graph; ixp_graph_launch replays it on
+ * `stream` with the same pointers and sizes (contents may change between
+ * launches).  Destroy with ixp_graph_destroy. */
+typedef struct ixp_graph_s *ixp_graph;
+int ixp_segmented_graph_create(ixp_graph *out, const void *keys, int32_t key_t,
+                               int64_t n, const int64_t *d_shape, int64_t m,
+                               const ixp_pred *pred, int32_t mode,
+                               void *out_keys, void *out_idx, int32_t idx_t,
+                               int64_t *d_seg_split, uint8_t *d_flags_out,
+                               const ixp_tuning *tune, void *ws,
+                               size_t ws_bytes);
+int ixp_graph_launch(ixp_graph g, void *stream);
+int ixp_graph_destroy(ixp_graph g);
+
+/* Blocking: synchronises `stream` and returns IXP_OK, or the error a kernel
+ * recorded in the workspace of the last call that used `ws` (IXP_EINVAL for a
+ * bad shape array, IXP_EDEVICE for an exhausted wait); then clears it. */
+int ixp_read_error(const void *ws, void *stream);
+
+/* ---- scatter / gather of rows (Section 2.1 scatter; Bij inverse) ----------- */
+
+/* dst[idx[i]] := vals[i] (rows of row_bytes bytes) for i in [0,m) with
+ * 0 <= idx[i] < n_dst; other indices are ignored, as scatter ignores
+ * out-of-bounds writes.  Precondition (not checked): Inj idx [0,n_dst), so no
+ * two rows race (scatter's idempotence requirement).  row_bytes must be a
+ * multiple of 4; multiples of 16 with 16-byte aligned buffers use vector
+ * stores.  Plain stores, no atomics. */
+int ixp_scatter_inj(void *dst, int64_t n_dst, const void *idx, int32_t idx_t,
+                    const void *vals, int64_t m, int64_t row_bytes,
+                    void *stream);
+
+/* dst[i] := src[idx[i]] for i in [0,m) (rows of row_bytes bytes).  An index
+ * outside [0,n_src) produces a zero row and, if d_err is not NULL, sets
+ * *d_err = 1 (device int32); the caller zeroes *d_err. */
+int ixp_gather(void *dst, const void *src, int64_t n_src, const void *idx,
+               int32_t idx_t, int64_t m, int64_t row_bytes, int32_t *d_err,
+               void *stream);
+
+/* ---- property checkers (Section 2.3, figure "Array Properties") ----------- */
+enum {
+    IXP_RANGE = 1,    /* lo <= X[i] < hi for all i                           */
+    IXP_MONO = 2,     /* X[i-1] op X[i] for 1 <= i < n                       */
+    IXP_INJ = 4,      /* no repeated value among entries inside [lo,hi)      */
+    IXP_BIJ = 8,      /* Inj, in-Rcd values inside Img, count = |Img|        */
+    IXP_FILTPART = 16 /* outputs of a flat partition are a filter-partition   */
+};
+enum { IXP_MONO_LE = 0, IXP_MONO_LT = 1, IXP_MONO_GE = 2, IXP_MONO_GT = 3 };
+
+/* One verdict per property, written to device memory:
+ *   holds = 1/0; first_violation = -1 if it holds, else the least failing
+ *   index (see the per-property definitions below); aux = a value naming the
+ *   failure.
+ *   RANGE: first i with X[i] outside [lo,hi); aux = X[i].
+ *   MONO:  first i >= 1 with !(X[i-1] op X[i]); aux = 0.
+ *   INJ:   first i with X[i] in [lo,hi) equal to some earlier X[j]; aux = X[i].
+ *   BIJ:   first i with X[i] in [lo,hi) repeated earlier or outside
+ *          [img_lo,img_hi) (aux = X[i]); failing only on the count:
+ *          first_violation = n, aux = least value of Img not attained.
+ *   FILTPART: X = the partitioned keys (fp_src, key type fp_key_t), Y =
+ *          fp_dst, Z = x (the index array), split = *fp_split (device int64),
+ *          pred / mode as given to ixp_partition.  aux = OR of failing
+ *          sub-checks: 1 split != #trues (#kept); 2 Z not a bijection onto
+ *          [0,n) (FILTER: kept Z not injective into [0,split), or a dropped
+ *          Z inside [0,split)); 4 class order (Z[i] < split iff p, PARTITION
+ *          only); 8 Z not strictly increasing inside a class (FILTER: among
+ *          kept elements); 16 Y[Z[i]] != X[i] bitwise.  first_violation = the
+ *          least index failing one of 2..16, n if only 1 fails.
+ * Intervals are half-open; Rcd [lo,hi) must span at most 2^40 values. */
+typedef struct {
+    int32_t holds;
+    int32_t reserved;
+    int64_t first_violation;
+    int64_t aux;
+} ixp_verdict;
+
+typedef struct {
+    int64_t lo, hi;            /* RANGE interval; INJ/BIJ restricted co-domain */
+    int64_t img_lo, img_hi;    /* BIJ image, inside [lo,hi)                     */
+    int32_t mono_op;           /* IXP_MONO_*                                    */
+    int32_t fp_mode;           /* IXP_MODE_* of the checked partition           */
+    const void *fp_src;        /* device keys that were partitioned             */
+    const void *fp_dst;        /* device partitioned keys                       */
+    int32_t fp_key_t;          /* IXP_I32 or IXP_F32                            */
+    int32_t reserved;
+    ixp_pred fp_pred;          /* the partition predicate                      */
+    const int64_t *fp_split;   /* device int64, the split point                 */
+} ixp_prop_args;
+
+size_t ixp_check_props_workspace(int64_t n, uint32_t mask,
+                                 const ixp_prop_args *a);
+
+/* Checks the properties selected by `mask` (IXP_* bits) on the device array
+ * x[0..n) of type x_t (IXP_I32 or IXP_I64) and writes d_out[b] for every bit b
+ * in 0..4 (unselected properties get holds = 1, first_violation = -1).
+ * Verdicts are deterministic: independent of scheduling and bit-exact with
+ * the definitions above. */
+int ixp_check_props(const void *x, int32_t x_t, int64_t n, uint32_t mask,
+                    const ixp_prop_args *a, ixp_verdict *d_out, void *ws,
+                    size_t ws_bytes, void *stream);
+
+/* ---- device information ----------------------------------------------------- */
+/* Number of compute units of the current device (cached), or a negative status. */
+int ixp_device_cus(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IXPART_H */

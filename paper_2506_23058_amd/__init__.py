@@ -1,0 +1,7 @@
+"""MI355X (gfx950) filter-partition library: stable partition / filter, flat
+and segmented, property checkers and a differentiable partition, as HIP
+kernels behind the C ABI of include/ixpart.h."""
+from ._lib import (MODE_FILTER, MODE_PARTITION, PRED_FLAGS, PRED_LT, PRED_MOD_EQ,  # noqa: F401
+                   RANGE, MONO, INJ, BIJ, FILTPART, MONO_LE, MONO_LT, MONO_GE, MONO_GT,
+                   IxpError, lib)
+from .ops import Pred, partition, read_error, workspace  # noqa: F401

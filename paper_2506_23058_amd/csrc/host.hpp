@@ -1,0 +1,64 @@
+// host.hpp -- host-side helpers shared by the C-ABI entry points.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/ixpart.h"
+
+namespace ixp {
+
+inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+inline bool aligned(const void *p, uintptr_t a) {
+    return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0;
+}
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+inline size_t round_up(size_t a, size_t b) { return (a + b - 1) / b * b; }
+
+// Launch status of the kernel just enqueued.
+inline int launch_status() {
+    return hipGetLastError() == hipSuccess ? IXP_OK : IXP_EHIP;
+}
+
+// Validated, device-ready form of ixp_pred.
+struct HostPred {
+    int kind;
+    uint64_t M;     // MOD_EQ: ceil(2^64 / d) mod 2^64
+    uint32_t d;
+    int64_t r;
+    float s;
+    const uint8_t *flags;
+};
+
+inline int check_pred(const ixp_pred *p, int32_t key_t, HostPred *out) {
+    if (!p) return IXP_EINVAL;
+    out->kind = p->kind;
+    out->flags = p->flags;
+    out->s = p->s;
+    out->r = p->r;
+    out->d = 1;
+    out->M = 0;
+    switch (p->kind) {
+    case IXP_PRED_MOD_EQ:
+        if (key_t != IXP_I32) return key_t == IXP_I64 ? IXP_EUNSUPPORTED : IXP_EINVAL;
+        if (p->d < 1 || p->d > 0xFFFFFFFFll) return IXP_EINVAL;
+        out->d = static_cast<uint32_t>(p->d);
+        out->M = ~0ull / out->d + 1;
+        return IXP_OK;
+    case IXP_PRED_LT:
+        return key_t == IXP_F32 ? IXP_OK : IXP_EINVAL;
+    case IXP_PRED_FLAGS:
+        if (key_t != IXP_I32 && key_t != IXP_F32) return IXP_EINVAL;
+        return p->flags ? IXP_OK : IXP_EINVAL;
+    default:
+        return IXP_EINVAL;
+    }
+}
+
+// Number of compute units of the current device, cached per device.
+int device_cus();
+
+}  // namespace ixp

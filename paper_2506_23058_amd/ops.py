@@ -1,0 +1,115 @@
+"""Python front end of the MI355X filter-partition library.
+
+Thin wrappers over the C ABI (include/ixpart.h): they allocate outputs and
+workspaces with torch on the input's device, pass raw device pointers and the
+current HIP stream, and check the returned status.  All computation happens in
+the library's HIP kernels.
+"""
+import ctypes
+from dataclasses import dataclass
+from typing import Optional
+
+import torch
+
+from . import _lib as L
+
+_KEY_T = {torch.int32: L.I32, torch.float32: L.F32, torch.int64: L.I64}
+_IDX_T = {torch.int32: L.I32, torch.int64: L.I64}
+
+
+@dataclass(frozen=True)
+class Pred:
+    """Predicate p of partition2 (Section 2.1): MOD_EQ (floor-mod of an int32
+    key by d equals r), LT (f32 key < s) or FLAGS (a u8 tensor, nonzero = true)."""
+    kind: int
+    d: int = 1
+    r: int = 0
+    s: float = 0.0
+    flags: Optional[torch.Tensor] = None
+
+    @staticmethod
+    def mod_eq(d: int, r: int) -> "Pred":
+        return Pred(L.PRED_MOD_EQ, d=int(d), r=int(r))
+
+    @staticmethod
+    def lt(s: float) -> "Pred":
+        return Pred(L.PRED_LT, s=float(s))
+
+    @staticmethod
+    def from_flags(flags: torch.Tensor) -> "Pred":
+        if flags.dtype == torch.bool:
+            flags = flags.view(torch.uint8)
+        return Pred(L.PRED_FLAGS, flags=flags.contiguous())
+
+    def c(self) -> L.ixp_pred:
+        p = L.ixp_pred()
+        p.kind = self.kind
+        p.d = self.d
+        p.r = self.r
+        p.s = self.s
+        p.flags = self.flags.data_ptr() if self.flags is not None else None
+        return p
+
+
+def _stream_ptr(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else t.data_ptr()
+
+
+_ws_cache = {}
+
+
+def workspace(nbytes: int, device, tag: str = "default") -> torch.Tensor:
+    """A cached device workspace of at least ``nbytes`` bytes (one per tag and
+    device; calls that share a tag must not overlap on different streams)."""
+    key = (str(device), tag)
+    buf = _ws_cache.get(key)
+    if buf is None or buf.numel() < nbytes:
+        buf = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+        _ws_cache[key] = buf
+    return buf
+
+
+def _check_dev(*ts):
+    for t in ts:
+        if t is not None and not t.is_cuda:
+            raise ValueError("tensors must live on a GPU")
+
+
+def partition(keys: torch.Tensor, pred: Pred, mode: int = L.MODE_PARTITION,
+              idx_dtype=torch.int64, want_keys: bool = True, want_idx: bool = True,
+              out_keys: Optional[torch.Tensor] = None, out_idx: Optional[torch.Tensor] = None,
+              split: Optional[torch.Tensor] = None):
+    """Stable partition (partition2) or filter of a 1-D int32/f32 tensor.
+
+    Returns (out_keys, out_idx, split) with split a 1-element int64 device
+    tensor holding T.  In FILTER mode out_keys has length n and only its first
+    T entries are written.
+    """
+    _check_dev(keys)
+    keys = keys.contiguous()
+    n = keys.numel()
+    dev = keys.device
+    if want_keys and out_keys is None:
+        out_keys = torch.empty_like(keys)
+    if want_idx and out_idx is None:
+        out_idx = torch.empty(n, dtype=idx_dtype, device=dev)
+    if split is None:
+        split = torch.empty(1, dtype=torch.int64, device=dev)
+    ws = workspace(L.lib().ixp_partition_workspace(n), dev, "partition")
+    pc = pred.c()
+    rc = L.lib().ixp_partition(
+        _ptr(keys), _KEY_T[keys.dtype], n, ctypes.byref(pc), mode,
+        _ptr(out_keys) if want_keys else None, _ptr(out_idx) if want_idx else None,
+        _IDX_T[idx_dtype if out_idx is None else out_idx.dtype], _ptr(split),
+        _ptr(ws), ws.numel(), _stream_ptr(dev))
+    L.check(rc, "ixp_partition")
+    return (out_keys if want_keys else None), (out_idx if want_idx else None), split
+
+
+def read_error(ws: torch.Tensor) -> int:
+    """Blocking: the device error recorded in a workspace (0 if none)."""
+    return L.lib().ixp_read_error(_ptr(ws), _stream_ptr(ws.device))
