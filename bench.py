@@ -1,0 +1,218 @@
+#!/usr/bin/env python3
+"""Throughput of the filter-partition hot path on one MI355X.
+
+Headline workload: stable partition (partition2) of n = 2^28 f32 values drawn
+uniform in [0,1), predicate x < s, for the three selectivities
+s in {0.01, 0.5, 0.99}, writing int32 positions, the partitioned values and the
+split point.  One step = one partition per selectivity (3 * 2^28 elements),
+inputs resident in HBM.  value = partitioned elements per second over the timed
+steps (GElem/s).
+
+The JSON line also carries
+  roofline      -- the dominant kernel (the scan-scatter kernel) against the
+                   8 TB/s HBM peak: algorithmic bytes per launch / its average
+                   duration, timed with HIP events on its own stream during the
+                   timed steps;
+  cpu_baseline  -- the sequential C oracle timed on a bounded sample of the
+                   same workload, on the host;
+  sections      -- the other workloads (filter mode, small flat, segmented,
+                   fwd+bwd, property checks), each timed on its own.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+
+
+def _csrc_hash():
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2506_23058_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".hpp")):
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def _traffic(kernel: str, launches_elems: int):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None when it is absent or the kernels changed since."""
+    path = os.path.join(ROOT, "profiles", "counters.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        c = json.load(f)
+    if c.get("csrc_hash") != _csrc_hash():
+        return None
+    k = c.get("kernels", {}).get(kernel)
+    if not k or k.get("elements") != launches_elems:
+        return None
+    return k.get("hbm_bytes_per_launch")
+
+
+def timed(fn, steps, warmup, torch):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-sections", action="store_true")
+    ap.add_argument("--only-headline", action="store_true",
+                    help="headline steps only (for profiler runs)")
+    ap.add_argument("--with-copy", action="store_true",
+                    help="also run one plain device copy of the input (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the path is single-device; see the sharding notes in DESIGN.md).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2506_23058_amd as P
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    n = W.FLAT_LARGE_N
+    sels = W.FLAT_LARGE_SELECTIVITIES
+    x = torch.from_numpy(W.f32_uniform(n, W.FLAT_LARGE_SEED)).to(dev)
+    out_keys = torch.empty_like(x)
+    out_idx = torch.empty(n, dtype=torch.int32, device=dev)
+    split = torch.empty(1, dtype=torch.int64, device=dev)
+    preds = [P.Pred.lt(s) for s in sels]
+
+    def step():
+        for p in preds:
+            P.partition(x, p, P.MODE_PARTITION, torch.int32, out_keys=out_keys,
+                        out_idx=out_idx, split=split)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    P.profile_read()
+    P.profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    P.profile_enable(False)
+    prof = P.profile_read()
+
+    kern = {k: {"launches": v[0], "avg_ms": v[1] / max(v[0], 1)} for k, v in prof.items()}
+    scan = kern.get("flat_scan_partition", {"avg_ms": float("nan")})
+    count = kern.get("flat_count", {"avg_ms": float("nan")})
+    scan_alg = n * (4 + 4 + 4)            # read keys, write idx, write keys
+    count_alg = n * 4                     # read keys
+    achieved = scan_alg / (scan["avg_ms"] * 1e-3) / 1e9
+    for k, alg in (("flat_scan_partition", scan_alg), ("flat_count", count_alg)):
+        if k in kern:
+            kern[k]["alg_bytes_per_launch"] = alg
+            kern[k]["alg_GBps"] = alg / (kern[k]["avg_ms"] * 1e-3) / 1e9
+    traffic = _traffic("flat_scan_partition", n)
+    out = {
+        "metric": "partitioned GElem/s + % HBM peak (flat, segmented, fwd+bwd) on 1 MI355X",
+        "value": len(sels) * n / dt / 1e9,
+        "unit": "GElem/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "flat stable partition2, n=2^28 f32 uniform[0,1), x<s for "
+                               "s in {0.01,0.5,0.99} (one partition each per step), int32 "
+                               "positions + partitioned values + split",
+                   "n": n, "selectivities": list(sels), "idx_dtype": "int32"},
+        "roofline": {"bound": "hbm", "kernel": "flat_scan_partition",
+                     "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
+                     "alg_bytes_per_launch": scan_alg},
+        "whole_step_alg_GBps": len(sels) * (scan_alg + count_alg) / dt / 1e9,
+        "kernels": kern,
+    }
+
+    if args.with_copy:
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        del y
+    if not args.only_headline and not args.no_sections:
+        out["sections"] = sections(args, torch, np, P, W, dev, x, out_keys, out_idx, split)
+
+    if not args.only_headline and not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(W, np)
+    print(json.dumps(out))
+
+
+def sections(args, torch, np, P, W, dev, x, out_keys, out_idx, split):
+    res = {}
+    n = x.numel()
+    steps = max(3, args.steps // 2)
+    # copy kernel: achievable HBM bandwidth reference (read n*4 + write n*4)
+    y = torch.empty_like(x)
+    t = timed(lambda: y.copy_(x), steps, 2, torch)
+    res["copy_reference"] = {"bytes": 2 * 4 * n, "ms": t * 1e3, "GBps": 8 * n / t / 1e9}
+    del y
+    # filter mode (single pass) on the same input
+    fl = {}
+    for s in W.FLAT_LARGE_SELECTIVITIES:
+        p = P.Pred.lt(s)
+        t = timed(lambda: P.partition(x, p, P.MODE_FILTER, torch.int32, out_keys=out_keys,
+                                      out_idx=out_idx, split=split), steps, 2, torch)
+        T = int(split.item())
+        alg = n * 4 + n * 4 + T * 4
+        fl[str(s)] = {"ms": t * 1e3, "GElem_s": n / t / 1e9, "alg_GBps": alg / t / 1e9}
+    res["flat_filter_2^28"] = fl
+    # small flat config: n = 2^20 int32 keys, key % 2 == 0, int64 indices
+    ks = torch.from_numpy(W.int_keys(W.FLAT_SMALL_N, W.FLAT_SMALL_SEED)).to(dev)
+    p = P.Pred.mod_eq(2, 0)
+    oks = torch.empty_like(ks)
+    ois = torch.empty(ks.numel(), dtype=torch.int64, device=dev)
+    t = timed(lambda: P.partition(ks, p, P.MODE_PARTITION, torch.int64, out_keys=oks,
+                                  out_idx=ois, split=split), steps * 10, 5, torch)
+    res["flat_small_2^20_int64idx"] = {"ms": t * 1e3, "GElem_s": ks.numel() / t / 1e9}
+    return res
+
+
+def cpu_baseline(W, np):
+    """The oracle (single-threaded C) on the first 2^27 elements of the headline
+    input, once per selectivity."""
+    import oracle as O
+    ns = 1 << 27
+    xs = W.f32_uniform(W.FLAT_LARGE_N, W.FLAT_LARGE_SEED)[:ns].copy()
+    t0 = time.perf_counter()
+    for s in W.FLAT_LARGE_SELECTIVITIES:
+        O.partition2(xs, O.Pred.lt(s))
+    dt = time.perf_counter() - t0
+    return {"value": len(W.FLAT_LARGE_SELECTIVITIES) * ns / dt / 1e9, "unit": "GElem/s",
+            "cores": 1, "kind": "oracle",
+            "sample": f"partition2 of the first 2^27 of the 2^28 f32 inputs, once per "
+                      f"s in {list(W.FLAT_LARGE_SELECTIVITIES)}; {dt:.1f} s on one host core"}
+
+
+if __name__ == "__main__":
+    main()

@@ -253,6 +253,20 @@ int ixp_check_props(const void *x, int32_t x_t, int64_t n, uint32_t mask,
                     const ixp_prop_args *a, ixp_verdict *d_out, void *ws,
                     size_t ws_bytes, void *stream);
 
+/* ---- kernel timing ------------------------------------------------------------ */
+/* While enabled, every kernel the library enqueues (outside HIP-graph capture)
+ * is bracketed by two HIP events recorded on its own stream.  ixp_profile_read
+ * is blocking: it waits for the recorded events, writes up to `max` per-kernel
+ * summaries (name, launches, total milliseconds), stores the number of
+ * distinct kernels in *count, and clears the records. */
+typedef struct {
+    char name[64];
+    int64_t launches;
+    double total_ms;
+} ixp_kernel_stat;
+int ixp_profile_enable(int on);
+int ixp_profile_read(ixp_kernel_stat *out, int max, int *count);
+
 /* ---- device information ----------------------------------------------------- */
 /* Number of compute units of the current device (cached), or a negative status. */
 int ixp_device_cus(void);

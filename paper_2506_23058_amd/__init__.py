@@ -4,4 +4,4 @@ kernels behind the C ABI of include/ixpart.h."""
 from ._lib import (MODE_FILTER, MODE_PARTITION, PRED_FLAGS, PRED_LT, PRED_MOD_EQ,  # noqa: F401
                    RANGE, MONO, INJ, BIJ, FILTPART, MONO_LE, MONO_LT, MONO_GE, MONO_GT,
                    IxpError, lib)
-from .ops import Pred, partition, read_error, workspace  # noqa: F401
+from .ops import Pred, partition, profile_enable, profile_read, read_error, workspace  # noqa: F401

@@ -32,6 +32,11 @@ class ixp_tuning(ctypes.Structure):
                 ("wgs_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
+class ixp_kernel_stat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 64), ("launches", ctypes.c_int64),
+                ("total_ms", ctypes.c_double)]
+
+
 class ixp_verdict(ctypes.Structure):
     _fields_ = [("holds", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("first_violation", ctypes.c_int64), ("aux", ctypes.c_int64)]
@@ -72,6 +77,8 @@ SIGNATURES = {
     "ixp_gather": (ctypes.c_int, [_P, _P, _I64, _P, _I32, _I64, _I64, _P, _P]),
     "ixp_check_props_workspace": (_SZ, [_I64, _U32, _PA]),
     "ixp_check_props": (ctypes.c_int, [_P, _I32, _I64, _U32, _PA, _P, _P, _SZ, _P]),
+    "ixp_profile_enable": (ctypes.c_int, [ctypes.c_int]),
+    "ixp_profile_read": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
 }
 
 _lib = None

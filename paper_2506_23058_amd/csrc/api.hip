@@ -1,5 +1,10 @@
 // api.hip -- status strings, device queries and error read-back.
+#include <atomic>
+#include <cstring>
+#include <map>
 #include <mutex>
+#include <string>
+#include <vector>
 
 #include "host.hpp"
 
@@ -24,7 +29,100 @@ int device_cus() {
     return cus;
 }
 
+namespace {
+std::atomic<int> g_prof{0};
+std::mutex g_prof_mu;
+struct ProfRec {
+    const char *name;
+    hipEvent_t a, b;
+};
+std::vector<ProfRec> g_recs;
+std::vector<hipEvent_t> g_pool;
+
+hipEvent_t take_event() {
+    std::lock_guard<std::mutex> lock(g_prof_mu);
+    if (!g_pool.empty()) {
+        hipEvent_t e = g_pool.back();
+        g_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+bool capturing(hipStream_t st) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess) return true;
+    return cs != hipStreamCaptureStatusNone;
+}
+}  // namespace
+
+bool profiling() { return g_prof.load(std::memory_order_relaxed) != 0; }
+
+ProfScope::ProfScope(const char *name, hipStream_t st) : name_(name), st_(st) {
+    if (!profiling() || capturing(st)) return;
+    hipEvent_t e = take_event();
+    if (e && hipEventRecord(e, st) == hipSuccess) ev0_ = e;
+}
+
+ProfScope::~ProfScope() {
+    if (!ev0_) return;
+    hipEvent_t e = take_event();
+    if (!e || hipEventRecord(e, st_) != hipSuccess) return;
+    std::lock_guard<std::mutex> lock(g_prof_mu);
+    g_recs.push_back({name_, static_cast<hipEvent_t>(ev0_), e});
+}
+
 }  // namespace ixp
+
+extern "C" int ixp_profile_enable(int on) {
+    ixp::g_prof.store(on ? 1 : 0);
+    return IXP_OK;
+}
+
+extern "C" int ixp_profile_read(ixp_kernel_stat *out, int max, int *count) {
+    using namespace ixp;
+    std::vector<ProfRec> recs;
+    {
+        std::lock_guard<std::mutex> lock(g_prof_mu);
+        recs.swap(g_recs);
+    }
+    std::map<std::string, std::pair<int64_t, double>> acc;
+    std::vector<std::string> order;
+    int rc = IXP_OK;
+    for (const ProfRec &r : recs) {
+        float ms = 0.f;
+        if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess)
+            rc = IXP_EHIP;
+        auto it = acc.find(r.name);
+        if (it == acc.end()) {
+            order.push_back(r.name);
+            it = acc.emplace(r.name, std::make_pair(int64_t{0}, 0.0)).first;
+        }
+        it->second.first += 1;
+        it->second.second += ms;
+    }
+    {
+        std::lock_guard<std::mutex> lock(g_prof_mu);
+        for (const ProfRec &r : recs) {
+            g_pool.push_back(r.a);
+            g_pool.push_back(r.b);
+        }
+    }
+    int k = 0;
+    for (const std::string &nm : order) {
+        if (out && k < max) {
+            std::memset(out[k].name, 0, sizeof(out[k].name));
+            std::strncpy(out[k].name, nm.c_str(), sizeof(out[k].name) - 1);
+            out[k].launches = acc[nm].first;
+            out[k].total_ms = acc[nm].second;
+        }
+        ++k;
+    }
+    if (count) *count = k;
+    return rc;
+}
 
 extern "C" const char *ixp_status_str(int status) {
     switch (status) {

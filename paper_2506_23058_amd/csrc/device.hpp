@@ -28,6 +28,11 @@ __device__ __forceinline__ uint32_t rank_below(uint64_t m) {
 
 __device__ __forceinline__ int lane_id() { return static_cast<int>(rank_below(~0ull)); }
 
+// Index of this thread's wave inside the workgroup, as a wave-uniform value.
+__device__ __forceinline__ int wave_id() {
+    return __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
+}
+
 // DPP row_ror:k control code (rotate right by k inside each 16-lane row).
 template <int K>
 __device__ __forceinline__ uint32_t dpp_row_ror(uint32_t v) {
@@ -125,12 +130,15 @@ __device__ __forceinline__ void set_error(int32_t *err, int32_t code) {
 constexpr uint32_t kSpinLimit = 1u << 22;
 
 // Decoupled look-back, executed by one full wave: the exclusive prefix of tile
-// `t` over the tiles [first, t) of the same scan.  Each step reads the 64
-// nearest unread predecessors at once (lane i reads tile j - i), waits while
-// any of them up to the nearest inclusive prefix is unpublished, and sums the
-// window with a DPP reduction.  Aggregates are below 2^32; an inclusive prefix
-// may be any 62-bit value and is added separately.  Tiles before `first`
-// behave as an inclusive prefix of 0.
+// `t` over the tiles [first, t) of the same scan.  Each round reads the
+// 64*LOADS nearest unread predecessors at once (lane i, load u reads tile
+// j - 64u - i), then walks the 64-wide windows in order: a window is summed
+// with a DPP reduction when every tile up to its nearest inclusive prefix has
+// published; at an unpublished one the walk re-reads from there (with a short
+// sleep).  Aggregates are below 2^32; an inclusive prefix may be any 62-bit
+// value and is added separately.  Tiles before `first` behave as an inclusive
+// prefix of 0.
+template <int LOADS = 4>
 __device__ __forceinline__ int64_t lookback(const uint64_t *desc, int64_t t,
                                             int64_t first, int32_t *err) {
     const int lane = lane_id();
@@ -138,31 +146,71 @@ __device__ __forceinline__ int64_t lookback(const uint64_t *desc, int64_t t,
     int64_t j = t - 1;
     uint32_t spins = 0;
     while (j >= first) {
-        const int64_t i = j - lane;
-        const uint64_t d = i >= first ? desc_load(desc + i) : kStP;
-        const uint32_t st = static_cast<uint32_t>(d >> 62);
-        const uint64_t mX = ballot(st == 0);
-        const uint64_t mP = ballot(st == 2);
-        const uint64_t upto = mP ? (((mP & (~mP + 1)) << 1) - 1) : ~0ull;
-        if (mX & upto) {
+        uint64_t d[LOADS];
+#pragma unroll
+        for (int u = 0; u < LOADS; ++u) {
+            const int64_t i = j - u * kWave - lane;
+            d[u] = i >= first ? desc_load(desc + i) : kStP;
+        }
+        bool done = false, stalled = false;
+#pragma unroll
+        for (int u = 0; u < LOADS; ++u) {
+            if (done || stalled) continue;
+            const uint32_t st = static_cast<uint32_t>(d[u] >> 62);
+            const uint64_t mX = ballot(st == 0);
+            const uint64_t mP = ballot(st == 2);
+            const uint64_t upto = mP ? (((mP & (~mP + 1)) << 1) - 1) : ~0ull;
+            if (mX & upto) {
+                stalled = true;
+                continue;
+            }
+            const int firstP = mP ? __builtin_ctzll(mP) : kWave;
+            const bool in = (upto >> lane) & 1ull;
+            const uint32_t small = (in && lane != firstP) ? static_cast<uint32_t>(d[u] & kValMask) : 0u;
+            excl += wave_sum_u32(small);
+            if (mP) {
+                excl += static_cast<int64_t>(readlane_u64(d[u] & kValMask, firstP));
+                done = true;
+            } else {
+                j -= kWave;
+            }
+        }
+        if (done) break;
+        if (stalled) {
             if (++spins > kSpinLimit) {
                 if (lane == 0) set_error(err, kErrSpin);
                 return excl;
             }
-            __builtin_amdgcn_s_sleep(2);
-            continue;
+            __builtin_amdgcn_s_sleep(1);
         }
-        const int firstP = mP ? __builtin_ctzll(mP) : kWave;
-        const bool in = (upto >> lane) & 1ull;
-        const uint32_t small = (in && lane != firstP) ? static_cast<uint32_t>(d & kValMask) : 0u;
-        excl += wave_sum_u32(small);
-        if (mP) {
-            excl += static_cast<int64_t>(readlane_u64(d & kValMask, firstP));
-            break;
-        }
-        j -= kWave;
     }
     return excl;
+}
+
+// ------------------------------------------------------------ streaming loads --
+// Input keys and flags are read exactly once: nontemporal loads keep them from
+// displacing reusable lines in the caches.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+template <int VEC>
+__device__ __forceinline__ void load_group(const uint32_t *p, uint32_t (&out)[VEC]) {
+    if constexpr (VEC == 4) {
+        const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p));
+        out[0] = v.x; out[1] = v.y; out[2] = v.z; out[3] = v.w;
+    } else {
+        out[0] = __builtin_nontemporal_load(p);
+    }
+}
+
+template <int VEC>
+__device__ __forceinline__ void load_flags(const uint8_t *p, uint8_t (&out)[VEC]) {
+    if constexpr (VEC == 4) {
+        const uint32_t w = __builtin_nontemporal_load(reinterpret_cast<const uint32_t *>(p));
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) out[q] = static_cast<uint8_t>(w >> (8 * q));
+    } else {
+        out[0] = *p;
+    }
 }
 
 // ----------------------------------------------------------------- the tile --
@@ -177,12 +225,12 @@ struct Tile {
     static constexpr int kSize = BLOCK * ROWS * VEC;
     static_assert(BLOCK % kWave == 0 && BLOCK <= 1024, "block");
     static_assert(VEC == 1 || VEC == 4, "vec");
-    static_assert(ROWS * VEC <= 32, "flag bits");
+    static_assert(ROWS * VEC <= 64, "flag bits");
 
     uint32_t key[ROWS][VEC];
     uint32_t rank[ROWS][VEC];   // exclusive rank among the tile's trues
-    uint32_t fbits = 0;         // bit r*VEC+q: element is valid and true
-    uint32_t vbits = 0;         // bit r*VEC+q: element is valid
+    uint64_t fbits = 0;         // bit r*VEC+q: element is valid and true
+    uint64_t vbits = 0;         // bit r*VEC+q: element is valid
     uint32_t wave_total = 0;    // trues of this wave (uniform)
 
     __device__ static __forceinline__ int64_t pos(int64_t base, int wave, int r, int lane, int q) {
@@ -190,58 +238,90 @@ struct Tile {
     }
 
     // Loads keys (if need_keys) and flag bytes (for a flag predicate) of the
-    // valid positions and evaluates the predicate.  Groups of VEC elements
-    // that lie fully inside [0, n) and are VEC-aligned use one vector load.
+    // valid positions and evaluates the predicate.
+    //
+    // Three paths, chosen per tile (wave-uniform): a full tile issues one
+    // unconditional nontemporal vector load per row from one base address; a
+    // partial tile (except one holding the array's incomplete last vector
+    // group) does the same, but rows that miss [lo, hi) re-read the group
+    // containing lo instead (a cache hit), so the loads still form one
+    // branch-free batch; the tile holding the incomplete last group uses
+    // element-wise guarded loads.
     template <class Pred>
     __device__ __forceinline__ void load(const uint32_t *keys, int64_t n, int64_t base,
                                          int64_t lo, int64_t hi, const Pred &pred,
                                          bool need_keys, int wave, int lane) {
+        const bool tail = VEC > 1 && (n & (VEC - 1)) != 0 && hi > (n & ~static_cast<int64_t>(VEC - 1));
+        uint32_t kv[ROWS][VEC];
+        uint8_t fv[ROWS][VEC];
+        if (base >= lo && base + kSize <= hi) {
+            // whole tile valid: plain strided addresses (immediate offsets)
+            const uint32_t *kp = keys + pos(base, wave, 0, lane, 0);
+            const uint8_t *fp = nullptr;
+            if constexpr (Pred::kUsesFlags) fp = pred.flags + pos(base, wave, 0, lane, 0);
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r) {
+                if (need_keys) load_group(kp + r * (kWave * VEC), kv[r]);
+                else {
+#pragma unroll
+                    for (int q = 0; q < VEC; ++q) kv[r][q] = 0;
+                }
+                if constexpr (Pred::kUsesFlags) load_flags(fp + r * (kWave * VEC), fv[r]);
+                else {
+#pragma unroll
+                    for (int q = 0; q < VEC; ++q) fv[r][q] = 0;
+                }
+            }
+        } else if (!tail) {
+            const int64_t park = lo & ~static_cast<int64_t>(VEC - 1);
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r) {
+                const int64_t p0 = pos(base, wave, r, lane, 0);
+                const bool live = p0 + VEC > lo && p0 < hi;
+                const int64_t src = live ? p0 : park;
+                if (need_keys) load_group(keys + src, kv[r]);
+                else {
+#pragma unroll
+                    for (int q = 0; q < VEC; ++q) kv[r][q] = 0;
+                }
+                if constexpr (Pred::kUsesFlags) load_flags(pred.flags + src, fv[r]);
+                else {
+#pragma unroll
+                    for (int q = 0; q < VEC; ++q) fv[r][q] = 0;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r) {
+                const int64_t p0 = pos(base, wave, r, lane, 0);
+#pragma unroll
+                for (int q = 0; q < VEC; ++q) {
+                    const int64_t p = p0 + q;
+                    const bool ok = p >= lo && p < hi;
+                    kv[r][q] = (need_keys && ok) ? keys[p] : 0u;
+                    if constexpr (Pred::kUsesFlags) fv[r][q] = ok ? pred.flags[p] : 0;
+                    else fv[r][q] = 0;
+                }
+            }
+        }
 #pragma unroll
         for (int r = 0; r < ROWS; ++r) {
             const int64_t p0 = pos(base, wave, r, lane, 0);
-            uint32_t kv[VEC];
-            uint8_t fv[VEC];
-#pragma unroll
-            for (int q = 0; q < VEC; ++q) { kv[q] = 0; fv[q] = 0; }
-            const bool any = p0 + VEC > lo && p0 < hi;
-            const bool full = p0 >= lo && p0 + VEC <= hi;
-            if (any) {
-                if (VEC == 4 && full) {
-                    if (need_keys) {
-                        const uint4 v = *reinterpret_cast<const uint4 *>(keys + p0);
-                        kv[0] = v.x; kv[1 % VEC] = v.y; kv[2 % VEC] = v.z; kv[3 % VEC] = v.w;
-                    }
-                    if constexpr (Pred::kUsesFlags) {
-                        const uint32_t w = *reinterpret_cast<const uint32_t *>(pred.flags + p0);
-#pragma unroll
-                        for (int q = 0; q < VEC; ++q) fv[q] = static_cast<uint8_t>(w >> (8 * q));
-                    }
-                } else {
-#pragma unroll
-                    for (int q = 0; q < VEC; ++q) {
-                        const int64_t p = p0 + q;
-                        if (p >= lo && p < hi) {
-                            if (need_keys) kv[q] = keys[p];
-                            if constexpr (Pred::kUsesFlags) fv[q] = pred.flags[p];
-                        }
-                    }
-                }
-            }
 #pragma unroll
             for (int q = 0; q < VEC; ++q) {
                 const int64_t p = p0 + q;
                 const bool valid = p >= lo && p < hi;
-                key[r][q] = kv[q];
-                const bool f = valid && pred(kv[q], fv[q]);
-                vbits |= static_cast<uint32_t>(valid) << (r * VEC + q);
-                fbits |= static_cast<uint32_t>(f) << (r * VEC + q);
+                key[r][q] = kv[r][q];
+                const bool f = valid && pred(kv[r][q], fv[r][q]);
+                vbits |= static_cast<uint64_t>(valid) << (r * VEC + q);
+                fbits |= static_cast<uint64_t>(f) << (r * VEC + q);
             }
         }
         (void)n;
     }
 
-    __device__ __forceinline__ bool flag(int r, int q) const { return (fbits >> (r * VEC + q)) & 1u; }
-    __device__ __forceinline__ bool valid(int r, int q) const { return (vbits >> (r * VEC + q)) & 1u; }
+    __device__ __forceinline__ bool flag(int r, int q) const { return (fbits >> (r * VEC + q)) & 1ull; }
+    __device__ __forceinline__ bool valid(int r, int q) const { return (vbits >> (r * VEC + q)) & 1ull; }
 
     // Ranks of the trues inside this wave's run, from one ballot per
     // (row, q): the rank of element (r, lane, q) counts the trues of earlier
@@ -304,7 +384,9 @@ struct Tile {
 template <int VEC, class Idx>
 __device__ __forceinline__ void store_idx_group(Idx *out, int64_t p0, const Idx (&v)[VEC],
                                                 uint32_t valid_mask) {
-    if (VEC == 4 && valid_mask == 0xFu) {
+    if (VEC == 1) {
+        if (valid_mask & 1u) out[p0] = v[0];
+    } else if (valid_mask == 0xFu) {
         if constexpr (sizeof(Idx) == 4) {
             uint4 w;
             w.x = static_cast<uint32_t>(v[0]); w.y = static_cast<uint32_t>(v[1 % VEC]);

@@ -8,33 +8,43 @@
 // #falses before i = i - E(i); the index map becomes
 //   idx[i] = c_i ? E(i) : T + i - E(i)            (T = num_true)
 // which is the closed form of `indices` the paper derives (Section 2.3).
+// Filter keeps only the trues: idx[i] = c_i ? E(i) : -1.
 //
-// Kernels, all on the caller's stream:
-//   init   -- zeroes the tile ticket, error word and split (and, for filter,
-//             the tile descriptors);
-//   count  -- (partition only) one wave per tile counts its trues, publishes
-//             the count as the tile's aggregate and adds it to T.  The stable
-//             order of the falses needs T before any false is placed;
-//   scan   -- one workgroup per tile, tiles taken in ticket order: flags by
-//             ballot, in-tile ranks by mbcnt, tile prefix by decoupled
-//             look-back, indices written in input order (vector stores),
-//             keys staged in LDS in output order and written as the tile's
-//             two contiguous runs.
+// Partition (three kernels on the caller's stream).  The falses cannot be
+// placed before T is known, so a counting pass comes first; it yields every
+// tile's true count, which makes a look-back unnecessary:
+//   count     -- one wave per tile (nontemporal vector loads, ballot +
+//                popcount), writes the tile's count;
+//   tile_scan -- one workgroup: exclusive scan of the tile counts (DPP wave
+//                scans), writes each tile's prefix, T and clears the error word;
+//   scatter   -- one workgroup per tile: flags by ballot, in-tile ranks by
+//                mbcnt, the tile prefix by one load; indices written in input
+//                order with vector stores, keys staged in LDS in output order
+//                and written as the tile's two contiguous runs.
+// Filter (single pass, two kernels):
+//   init      -- clears the tile descriptors, ticket and error word;
+//   scan      -- tiles taken in ticket order; each publishes its count, finds
+//                its prefix by decoupled look-back over the descriptors,
+//                publishes its inclusive prefix, then writes as above.  The
+//                last tile writes T.
 #include "device.hpp"
 #include "host.hpp"
 
 namespace ixp {
 namespace {
 
-constexpr int kFlatBlock = 256;
 constexpr size_t kWsHeader = 256;   // ticket (u32), error word (i32), padding
 
-template <int VEC>
+// Tile geometry.  Partition: 256 threads x 4 rows x 4 = 4096 elements per
+// tile (the count kernel uses the same tiles).  Filter: 512 x 4 x 4 = 8192, so
+// that tiles start slowly enough for one look-back round to reach a published
+// inclusive prefix.  Unaligned buffers use one-element groups (VEC = 1).
+template <int MODE, int VEC>
 struct FlatCfg {
-    static constexpr int kBlock = kFlatBlock;
+    static constexpr int kBlock = MODE == IXP_MODE_PARTITION ? 256 : 512;
     static constexpr int kRows = VEC == 4 ? 4 : 16;
     using T = Tile<kBlock, kRows, VEC>;
-    static constexpr int kTile = T::kSize;   // 4096 for both widths
+    static constexpr int kTile = T::kSize;
 };
 
 struct FlatArgs {
@@ -47,113 +57,142 @@ struct FlatArgs {
     uint32_t *ticket;
     int32_t *err;
     int64_t num_tiles;
+    int64_t *wsum;            // partition: per counting wave total, then prefix
+    int64_t tiles_per_wave;   // partition: tiles owned by one counting wave
     int32_t need_keys;
 };
 
-__global__ void flat_init_kernel(uint32_t *ticket, int32_t *err, int64_t *split,
-                                 uint64_t *desc, int64_t num_desc) {
+// Counting waves per partition call (fixed, so the workspace size does not
+// depend on the device).
+constexpr int64_t kCountWaves = 8192;
+
+__global__ void flat_init_kernel(uint32_t *ticket, int32_t *err, uint64_t *desc, int64_t num_desc) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i == 0) {
         *ticket = 0;
         *err = 0;
-        *split = 0;
     }
     for (int64_t j = i; j < num_desc; j += static_cast<int64_t>(gridDim.x) * blockDim.x)
         desc[j] = 0;
 }
 
-// One wave counts one tile (same tile bounds as the scan kernel) and
-// publishes the count as that tile's aggregate; each wave adds its running
-// total to T once at the end.
+// Counting: wave w owns the contiguous tiles [w*k, w*k + k) (k =
+// tiles_per_wave).  It counts them in order, 1024 elements at a time, writes
+// each tile's exclusive prefix inside the run to desc[t] and the run total to
+// wsum[w].
 template <int VEC, class Pred>
-__global__ __launch_bounds__(kFlatBlock) void flat_count_kernel(FlatArgs a, Pred pred) {
-    constexpr int kTile = FlatCfg<VEC>::kTile;
-    constexpr int kSteps = kTile / (kWave * VEC);
+__global__ __launch_bounds__(256) void flat_count_kernel(FlatArgs a, Pred pred) {
+    constexpr int kTile = FlatCfg<IXP_MODE_PARTITION, VEC>::kTile;
+    using WT = Tile<kWave, (VEC == 4 ? 4 : 16), VEC>;
+    constexpr int kChunks = kTile / WT::kSize;
+    static_assert(kChunks * WT::kSize == kTile, "count chunks");
     const int lane = threadIdx.x & (kWave - 1);
-    const int64_t wave0 = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
-    const int64_t nwaves = (static_cast<int64_t>(gridDim.x) * blockDim.x) >> 6;
-    uint64_t mine = 0;
-    for (int64_t t = wave0; t < a.num_tiles; t += nwaves) {
+    const int64_t w = static_cast<int64_t>(blockIdx.x) * (256 / kWave) + wave_id();
+    const int64_t t0 = w * a.tiles_per_wave;
+    const int64_t t1 = t0 + a.tiles_per_wave < a.num_tiles ? t0 + a.tiles_per_wave : a.num_tiles;
+    uint64_t run = 0;
+    for (int64_t t = t0; t < t1; ++t) {
         const int64_t lo = t * kTile;
         const int64_t hi = lo + kTile < a.n ? lo + kTile : a.n;
         uint32_t cnt = 0;
-#pragma unroll
-        for (int k = 0; k < kSteps; ++k) {
-            const int64_t p0 = lo + static_cast<int64_t>(k) * (kWave * VEC) + lane * VEC;
-            uint32_t kv[VEC];
-            uint8_t fv[VEC];
-#pragma unroll
-            for (int q = 0; q < VEC; ++q) { kv[q] = 0; fv[q] = 0; }
-            if (VEC == 4 && p0 + VEC <= hi) {
-                if (!Pred::kUsesFlags) {
-                    const uint4 v = *reinterpret_cast<const uint4 *>(a.keys + p0);
-                    kv[0] = v.x; kv[1 % VEC] = v.y; kv[2 % VEC] = v.z; kv[3 % VEC] = v.w;
-                } else if constexpr (Pred::kUsesFlags) {
-                    const uint32_t w = *reinterpret_cast<const uint32_t *>(pred.flags + p0);
-#pragma unroll
-                    for (int q = 0; q < VEC; ++q) fv[q] = static_cast<uint8_t>(w >> (8 * q));
-                }
-            } else {
-#pragma unroll
-                for (int q = 0; q < VEC; ++q) {
-                    if (p0 + q < hi) {
-                        if constexpr (Pred::kUsesFlags) fv[q] = pred.flags[p0 + q];
-                        else kv[q] = a.keys[p0 + q];
-                    }
-                }
-            }
-#pragma unroll
-            for (int q = 0; q < VEC; ++q) {
-                const bool f = p0 + q < hi && pred(kv[q], fv[q]);
-                cnt += static_cast<uint32_t>(__builtin_popcountll(ballot(f)));
-            }
+        for (int c = 0; c < kChunks; ++c) {
+            WT chunk;
+            chunk.load(a.keys, a.n, lo + c * WT::kSize, lo, hi, pred, !Pred::kUsesFlags, 0, lane);
+            cnt += chunk.wave_count();
         }
-        if (lane == 0) desc_store(a.desc + t, kStA | cnt);
-        mine += cnt;
+        if (lane == 0) a.desc[t] = run;
+        run += cnt;
     }
-    if (lane == 0 && mine)
-        atomicAdd(reinterpret_cast<unsigned long long *>(a.split),
-                  static_cast<unsigned long long>(mine));
+    if (lane == 0 && w < kCountWaves) a.wsum[w] = static_cast<int64_t>(run);
+}
+
+// One workgroup of 1024 threads turns wsum[0..nw) from run totals into
+// exclusive prefixes (in place) and writes T.  Thread i owns nw/1024
+// consecutive entries; the 1024 partial sums are scanned in LDS (64-bit,
+// Hillis-Steele).
+__global__ __launch_bounds__(1024) void flat_tile_scan_kernel(int64_t *wsum, int64_t nw,
+                                                              int64_t *split, int32_t *err) {
+    __shared__ int64_t buf[2][1024];
+    const int tid = threadIdx.x;
+    const int64_t per = (nw + 1023) / 1024;
+    const int64_t b = tid * per < nw ? tid * per : nw;
+    const int64_t e = b + per < nw ? b + per : nw;
+    int64_t run = 0;
+    for (int64_t i = b; i < e; ++i) run += wsum[i];
+    int cur = 0;
+    buf[cur][tid] = run;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int64_t v = buf[cur][tid] + (tid >= off ? buf[cur][tid - off] : 0);
+        buf[cur ^ 1][tid] = v;
+        cur ^= 1;
+        __syncthreads();
+    }
+    int64_t acc = buf[cur][tid] - run;   // exclusive prefix of this thread's entries
+    for (int64_t i = b; i < e; ++i) {
+        const int64_t c = wsum[i];
+        wsum[i] = acc;
+        acc += c;
+    }
+    if (tid == 1023) {
+        *split = buf[cur][1023];
+        *err = 0;
+    }
 }
 
 template <int VEC, class Pred, int MODE, class Idx>
-__global__ __launch_bounds__(kFlatBlock) void flat_scan_kernel(FlatArgs a, Pred pred) {
-    using T = typename FlatCfg<VEC>::T;
+__global__ __launch_bounds__((FlatCfg<MODE, VEC>::kBlock)) void flat_scan_kernel(FlatArgs a, Pred pred) {
+    using Cfg = FlatCfg<MODE, VEC>;
+    using T = typename Cfg::T;
     constexpr int kTile = T::kSize;
-    constexpr int kRows = FlatCfg<VEC>::kRows;
+    constexpr int kRows = Cfg::kRows;
+    constexpr int kBlock = Cfg::kBlock;
     __shared__ uint32_t stage[kTile];
     __shared__ uint32_t wtot[T::kWaves];
     __shared__ int64_t sh[2];
 
     const int tid = threadIdx.x;
-    const int wave = tid >> 6;
+    const int wave = wave_id();
     const int lane = tid & (kWave - 1);
-    if (tid == 0) sh[0] = atomicAdd(a.ticket, 1u);
-    __syncthreads();
-    const int64_t t = sh[0];
+    int64_t t;
+    if (MODE == IXP_MODE_PARTITION) {
+        t = blockIdx.x;
+    } else {
+        if (tid == 0) sh[0] = atomicAdd(a.ticket, 1u);
+        __syncthreads();
+        t = sh[0];
+    }
     const int64_t lo = t * kTile;
     const int64_t hi = lo + kTile < a.n ? lo + kTile : a.n;
+    // partition: the tile prefix and T are ready before the kernel starts
+    int64_t excl = 0, total = 0;
+    if (MODE == IXP_MODE_PARTITION) {
+        excl = static_cast<int64_t>(a.desc[t]) + a.wsum[t / a.tiles_per_wave];
+        total = *a.split;
+    }
 
     T tile;
     tile.load(a.keys, a.n, lo, lo, hi, pred, a.need_keys != 0, wave, lane);
     tile.wave_ranks();
     const uint32_t tcount = tile.block_ranks(wtot, wave, lane);
 
-    if (MODE == IXP_MODE_FILTER && tid == 0 && t > 0) desc_store(a.desc + t, kStA | tcount);
-    if (wave == 0) {
-        const int64_t excl = t == 0 ? 0 : lookback(a.desc, t, 0, a.err);
-        if (lane == 0) {
-            desc_store(a.desc + t, kStP | static_cast<uint64_t>(excl + tcount));
-            sh[1] = excl;
-            if (MODE == IXP_MODE_FILTER && t == a.num_tiles - 1) *a.split = excl + tcount;
+    if (MODE == IXP_MODE_FILTER) {
+        if (tid == 0 && t > 0) desc_store(a.desc + t, kStA | tcount);
+        if (wave == 0) {
+            const int64_t e = t == 0 ? 0 : lookback<4>(a.desc, t, 0, a.err);
+            if (lane == 0) {
+                desc_store(a.desc + t, kStP | static_cast<uint64_t>(e + tcount));
+                sh[1] = e;
+                if (t == a.num_tiles - 1) *a.split = e + tcount;
+            }
         }
+        __syncthreads();
+        excl = sh[1];
     }
-    __syncthreads();
-    const int64_t excl = sh[1];
-    const int64_t total = MODE == IXP_MODE_PARTITION ? __hip_atomic_load(a.split, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
     const int64_t false_base = total + (lo - excl);   // T + #falses before the tile
 
     Idx *out_idx = static_cast<Idx *>(a.out_idx);
+    const bool full = hi - lo == kTile;   // wave-uniform
 #pragma unroll
     for (int r = 0; r < kRows; ++r) {
         const int64_t p0 = T::pos(lo, wave, r, lane, 0);
@@ -173,13 +212,16 @@ __global__ __launch_bounds__(kFlatBlock) void flat_scan_kernel(FlatArgs a, Pred 
             if (a.out_keys && ok && (MODE == IXP_MODE_PARTITION || f))
                 stage[f ? rt : tcount + rf] = tile.key[r][q];
         }
-        if (out_idx && vm) store_idx_group<VEC, Idx>(out_idx, p0, v, vm);
+        if (out_idx) {
+            if (full) store_idx_group<VEC, Idx>(out_idx, p0, v, (1u << VEC) - 1);
+            else if (vm) store_idx_group<VEC, Idx>(out_idx, p0, v, vm);
+        }
     }
     if (a.out_keys) {
         __syncthreads();
         const int64_t nvalid = hi - lo;
         const int64_t nout = MODE == IXP_MODE_PARTITION ? nvalid : static_cast<int64_t>(tcount);
-        for (int64_t s = tid; s < nout; s += kFlatBlock) {
+        for (int64_t s = tid; s < nout; s += kBlock) {
             const int64_t dst = s < tcount ? excl + s : false_base + (s - tcount);
             if (dst < a.n) a.out_keys[dst] = stage[s];
         }
@@ -187,28 +229,47 @@ __global__ __launch_bounds__(kFlatBlock) void flat_scan_kernel(FlatArgs a, Pred 
 }
 
 template <int VEC, class Pred>
-int launch_flat(const FlatArgs &a, const Pred &pred, int mode, int idx_t, hipStream_t st) {
-    const int64_t nt = a.num_tiles;
+int launch_flat(FlatArgs a, const Pred &pred, int mode, int idx_t, hipStream_t st) {
+    const int64_t n = a.n;
     if (mode == IXP_MODE_PARTITION) {
-        const int64_t cap = static_cast<int64_t>(device_cus()) * 8;
-        const int64_t waves_per_block = kFlatBlock / kWave;
-        const int64_t blocks = ceil_div(nt, waves_per_block) < cap ? ceil_div(nt, waves_per_block) : cap;
-        hipLaunchKernelGGL((flat_count_kernel<VEC, Pred>), dim3(static_cast<uint32_t>(blocks)),
-                           dim3(kFlatBlock), 0, st, a, pred);
-        if (launch_status() != IXP_OK) return IXP_EHIP;
+        using Cfg = FlatCfg<IXP_MODE_PARTITION, VEC>;
+        a.num_tiles = ceil_div(n, Cfg::kTile);
+        const int64_t nt = a.num_tiles;
+        int64_t nw = 0;
+        if (nt > 0) {
+            a.tiles_per_wave = ceil_div(nt, kCountWaves);
+            nw = ceil_div(nt, a.tiles_per_wave);
+            IXP_LAUNCH("flat_count", (flat_count_kernel<VEC, Pred>),
+                       dim3(static_cast<uint32_t>(ceil_div(nw, 4))), dim3(256), 0, st, a, pred);
+        }
+        IXP_LAUNCH("flat_tile_scan", flat_tile_scan_kernel, dim3(1), dim3(1024), 0, st, a.wsum, nw,
+                   a.split, a.err);
+        if (nt == 0) return launch_status();
         if (idx_t == IXP_I32)
-            hipLaunchKernelGGL((flat_scan_kernel<VEC, Pred, IXP_MODE_PARTITION, int32_t>),
-                               dim3(static_cast<uint32_t>(nt)), dim3(kFlatBlock), 0, st, a, pred);
+            IXP_LAUNCH("flat_scatter_partition", (flat_scan_kernel<VEC, Pred, IXP_MODE_PARTITION, int32_t>),
+                       dim3(static_cast<uint32_t>(nt)), dim3(Cfg::kBlock), 0, st, a, pred);
         else
-            hipLaunchKernelGGL((flat_scan_kernel<VEC, Pred, IXP_MODE_PARTITION, int64_t>),
-                               dim3(static_cast<uint32_t>(nt)), dim3(kFlatBlock), 0, st, a, pred);
+            IXP_LAUNCH("flat_scatter_partition", (flat_scan_kernel<VEC, Pred, IXP_MODE_PARTITION, int64_t>),
+                       dim3(static_cast<uint32_t>(nt)), dim3(Cfg::kBlock), 0, st, a, pred);
     } else {
+        using Cfg = FlatCfg<IXP_MODE_FILTER, VEC>;
+        a.num_tiles = ceil_div(n, Cfg::kTile);
+        const int64_t nt = a.num_tiles;
+        const int64_t iblocks = nt > 0 ? (ceil_div(nt, 256) < 1024 ? ceil_div(nt, 256) : 1024) : 1;
+        IXP_LAUNCH("flat_init", flat_init_kernel, dim3(static_cast<uint32_t>(iblocks)), dim3(256), 0, st,
+                   a.ticket, a.err, a.desc, nt);
+        if (nt == 0) {
+            // T = 0: let the tile scan of zero tiles write it
+            IXP_LAUNCH("flat_tile_scan", flat_tile_scan_kernel, dim3(1), dim3(1024), 0, st, a.wsum,
+                       int64_t{0}, a.split, a.err);
+            return launch_status();
+        }
         if (idx_t == IXP_I32)
-            hipLaunchKernelGGL((flat_scan_kernel<VEC, Pred, IXP_MODE_FILTER, int32_t>),
-                               dim3(static_cast<uint32_t>(nt)), dim3(kFlatBlock), 0, st, a, pred);
+            IXP_LAUNCH("flat_scan_filter", (flat_scan_kernel<VEC, Pred, IXP_MODE_FILTER, int32_t>),
+                       dim3(static_cast<uint32_t>(nt)), dim3(Cfg::kBlock), 0, st, a, pred);
         else
-            hipLaunchKernelGGL((flat_scan_kernel<VEC, Pred, IXP_MODE_FILTER, int64_t>),
-                               dim3(static_cast<uint32_t>(nt)), dim3(kFlatBlock), 0, st, a, pred);
+            IXP_LAUNCH("flat_scan_filter", (flat_scan_kernel<VEC, Pred, IXP_MODE_FILTER, int64_t>),
+                       dim3(static_cast<uint32_t>(nt)), dim3(Cfg::kBlock), 0, st, a, pred);
     }
     return launch_status();
 }
@@ -233,16 +294,16 @@ int dispatch_pred(const FlatArgs &a, const HostPred &hp, int mode, int idx_t, hi
 
 }  // namespace
 
-int64_t flat_tile_size() { return FlatCfg<4>::kTile; }
-
 }  // namespace ixp
 
 using namespace ixp;
 
+// The workspace holds one descriptor per tile of the smallest tile size in use.
 extern "C" size_t ixp_partition_workspace(int64_t n) {
     if (n < 0) return 0;
-    const int64_t nt = ceil_div(n, FlatCfg<4>::kTile);
-    return kWsHeader + round_up(static_cast<size_t>(nt) * sizeof(uint64_t), 256);
+    const int64_t nt = ceil_div(n, FlatCfg<IXP_MODE_PARTITION, 1>::kTile);
+    return kWsHeader + kCountWaves * sizeof(int64_t) +
+           round_up(static_cast<size_t>(nt) * sizeof(uint64_t), 256);
 }
 
 extern "C" int ixp_partition(const void *keys, int32_t key_t, int64_t n, const ixp_pred *pred,
@@ -274,16 +335,11 @@ extern "C" int ixp_partition(const void *keys, int32_t key_t, int64_t n, const i
     a.split = d_split;
     a.ticket = reinterpret_cast<uint32_t *>(w);
     a.err = reinterpret_cast<int32_t *>(w + 4);
-    a.desc = reinterpret_cast<uint64_t *>(w + kWsHeader);
-    a.num_tiles = ceil_div(n, FlatCfg<4>::kTile);
+    a.wsum = reinterpret_cast<int64_t *>(w + kWsHeader);
+    a.desc = reinterpret_cast<uint64_t *>(w + kWsHeader + kCountWaves * sizeof(int64_t));
+    a.num_tiles = 0;
+    a.tiles_per_wave = 1;
     a.need_keys = need_keys ? 1 : 0;
-
-    const int64_t ndesc = mode == IXP_MODE_FILTER ? a.num_tiles : 0;
-    const int64_t iblocks = ndesc > 0 ? (ceil_div(ndesc, 256) < 1024 ? ceil_div(ndesc, 256) : 1024) : 1;
-    hipLaunchKernelGGL(flat_init_kernel, dim3(static_cast<uint32_t>(iblocks)), dim3(256), 0, st,
-                       a.ticket, a.err, a.split, a.desc, ndesc);
-    if (launch_status() != IXP_OK) return IXP_EHIP;
-    if (n == 0) return IXP_OK;
 
     const bool vec4 = aligned(keys, 16) && aligned(out_idx, 16) &&
                       (hp.kind != IXP_PRED_FLAGS || aligned(hp.flags, 4));

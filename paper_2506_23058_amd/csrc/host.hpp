@@ -61,4 +61,22 @@ inline int check_pred(const ixp_pred *p, int32_t key_t, HostPred *out) {
 // Number of compute units of the current device, cached per device.
 int device_cus();
 
+// Kernel timing: while profiling is enabled, a ProfScope records a HIP event
+// on `st` at construction and another at destruction, around one launch.
+bool profiling();
+struct ProfScope {
+    ProfScope(const char *name, hipStream_t st);
+    ~ProfScope();
+    const char *name_;
+    hipStream_t st_;
+    void *ev0_ = nullptr;
+};
+
 }  // namespace ixp
+
+// Enqueues a kernel, timed when profiling is on.
+#define IXP_LAUNCH(name, kernel, grid, block, shmem, stream, ...)              \
+    do {                                                                      \
+        ::ixp::ProfScope ixp_prof_scope_(name, stream);                       \
+        hipLaunchKernelGGL(kernel, grid, block, shmem, stream, __VA_ARGS__);  \
+    } while (0)

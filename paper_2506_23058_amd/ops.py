@@ -113,3 +113,18 @@ def partition(keys: torch.Tensor, pred: Pred, mode: int = L.MODE_PARTITION,
 def read_error(ws: torch.Tensor) -> int:
     """Blocking: the device error recorded in a workspace (0 if none)."""
     return L.lib().ixp_read_error(_ptr(ws), _stream_ptr(ws.device))
+
+
+def profile_enable(on: bool = True):
+    """Bracket every library kernel with HIP events on its own stream."""
+    L.check(L.lib().ixp_profile_enable(1 if on else 0), "ixp_profile_enable")
+
+
+def profile_read():
+    """Blocking: {kernel name: (launches, total ms)} since the last read."""
+    buf = (L.ixp_kernel_stat * 64)()
+    cnt = ctypes.c_int(0)
+    L.check(L.lib().ixp_profile_read(ctypes.cast(buf, ctypes.c_void_p), 64, ctypes.byref(cnt)),
+            "ixp_profile_read")
+    return {buf[i].name.decode(): (int(buf[i].launches), float(buf[i].total_ms))
+            for i in range(min(cnt.value, 64))}
