@@ -4,4 +4,5 @@ kernels behind the C ABI of include/ixpart.h."""
 from ._lib import (MODE_FILTER, MODE_PARTITION, PRED_FLAGS, PRED_LT, PRED_MOD_EQ,  # noqa: F401
                    RANGE, MONO, INJ, BIJ, FILTPART, MONO_LE, MONO_LT, MONO_GE, MONO_GT,
                    IxpError, lib)
-from .ops import Pred, partition, profile_enable, profile_read, read_error, workspace  # noqa: F401
+from .ops import (Pred, SegmentedGraph, partition, profile_enable, profile_read,  # noqa: F401
+                  read_error, segmented_error, segmented_partition, tune_segmented, workspace)

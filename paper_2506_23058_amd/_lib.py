@@ -10,7 +10,7 @@ import os
 import torch  # noqa: F401  (loads the HIP runtime the library shares with torch)
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libixpart.so")
+LIB_PATH = os.environ.get("IXP_LIB", os.path.join(_HERE, "libixpart.so"))
 
 IXP_OK, IXP_EINVAL, IXP_ENOMEM, IXP_EHIP, IXP_EUNSUPPORTED, IXP_EWORKSPACE, IXP_EDEVICE = \
     0, -1, -2, -3, -4, -5, -6

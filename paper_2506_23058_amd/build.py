@@ -12,8 +12,8 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
-OUT = os.path.join(HERE, "libixpart.so")
-BUILD = os.path.join(HERE, "_build")
+OUT = os.environ.get("IXP_LIB_OUT", os.path.join(HERE, "libixpart.so"))
+BUILD = os.environ.get("IXP_BUILD_DIR", os.path.join(HERE, "_build"))
 ARCH = os.environ.get("IXP_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -21,7 +21,7 @@ CFLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",
-]
+] + os.environ.get("IXP_EXTRA_CFLAGS", "").split()
 
 
 def _compile(src: str) -> str:

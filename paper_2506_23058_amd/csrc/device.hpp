@@ -213,6 +213,21 @@ __device__ __forceinline__ void load_flags(const uint8_t *p, uint8_t (&out)[VEC]
     }
 }
 
+// Outputs are written once and not read again by the kernel: stores may be
+// marked nontemporal (streamed past the caches).
+#ifndef IXP_NT_STORES
+#define IXP_NT_STORES 1
+#endif
+
+template <class T>
+__device__ __forceinline__ void stream_store(T *p, T v) {
+#if IXP_NT_STORES
+    __builtin_nontemporal_store(v, p);
+#else
+    *p = v;
+#endif
+}
+
 // ----------------------------------------------------------------- the tile --
 // A tile is BLOCK threads x ROWS rows x VEC consecutive elements.  Wave w owns
 // the contiguous run [base + w*ROWS*64*VEC, +ROWS*64*VEC); inside it row r,
@@ -384,25 +399,26 @@ struct Tile {
 template <int VEC, class Idx>
 __device__ __forceinline__ void store_idx_group(Idx *out, int64_t p0, const Idx (&v)[VEC],
                                                 uint32_t valid_mask) {
+    typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
     if (VEC == 1) {
-        if (valid_mask & 1u) out[p0] = v[0];
+        if (valid_mask & 1u) stream_store(out + p0, v[0]);
     } else if (valid_mask == 0xFu) {
         if constexpr (sizeof(Idx) == 4) {
-            uint4 w;
+            u32x4 w;
             w.x = static_cast<uint32_t>(v[0]); w.y = static_cast<uint32_t>(v[1 % VEC]);
             w.z = static_cast<uint32_t>(v[2 % VEC]); w.w = static_cast<uint32_t>(v[3 % VEC]);
-            *reinterpret_cast<uint4 *>(out + p0) = w;
+            stream_store(reinterpret_cast<u32x4 *>(out + p0), w);
         } else {
-            ulonglong2 a, b;
+            u64x2 a, b;
             a.x = static_cast<uint64_t>(v[0]); a.y = static_cast<uint64_t>(v[1 % VEC]);
             b.x = static_cast<uint64_t>(v[2 % VEC]); b.y = static_cast<uint64_t>(v[3 % VEC]);
-            reinterpret_cast<ulonglong2 *>(out + p0)[0] = a;
-            reinterpret_cast<ulonglong2 *>(out + p0)[1] = b;
+            stream_store(reinterpret_cast<u64x2 *>(out + p0), a);
+            stream_store(reinterpret_cast<u64x2 *>(out + p0) + 1, b);
         }
     } else {
 #pragma unroll
         for (int q = 0; q < VEC; ++q)
-            if ((valid_mask >> q) & 1u) out[p0 + q] = v[q];
+            if ((valid_mask >> q) & 1u) stream_store(out + p0 + q, v[q]);
     }
 }
 

@@ -106,36 +106,50 @@ __global__ __launch_bounds__(256) void flat_count_kernel(FlatArgs a, Pred pred) 
     if (lane == 0 && w < kCountWaves) a.wsum[w] = static_cast<int64_t>(run);
 }
 
-// One workgroup of 1024 threads turns wsum[0..nw) from run totals into
-// exclusive prefixes (in place) and writes T.  Thread i owns nw/1024
-// consecutive entries; the 1024 partial sums are scanned in LDS (64-bit,
-// Hillis-Steele).
+// One workgroup of 1024 threads turns wsum[0..nw) (nw <= 8 * 1024) from run
+// totals into exclusive prefixes, in place, and writes T.  Thread i holds the
+// 8 consecutive entries [8i, 8i+8) in registers; the thread sums are scanned
+// inside each wave with shuffles and across the 16 waves through LDS.
 __global__ __launch_bounds__(1024) void flat_tile_scan_kernel(int64_t *wsum, int64_t nw,
                                                               int64_t *split, int32_t *err) {
-    __shared__ int64_t buf[2][1024];
+    constexpr int kPer = 8;
+    static_assert(kPer * 1024 >= kCountWaves, "scan capacity");
+    __shared__ int64_t wtot[16];
     const int tid = threadIdx.x;
-    const int64_t per = (nw + 1023) / 1024;
-    const int64_t b = tid * per < nw ? tid * per : nw;
-    const int64_t e = b + per < nw ? b + per : nw;
+    const int lane = tid & 63;
+    const int wave = wave_id();
+    int64_t v[kPer];
     int64_t run = 0;
-    for (int64_t i = b; i < e; ++i) run += wsum[i];
-    int cur = 0;
-    buf[cur][tid] = run;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int64_t i = static_cast<int64_t>(tid) * kPer + k;
+        v[k] = i < nw ? wsum[i] : 0;
+        run += v[k];
+    }
+    int64_t inc = run;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int64_t o = __shfl_up(inc, off, 64);
+        if (lane >= off) inc += o;
+    }
+    if (lane == 63) wtot[wave] = inc;
     __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        const int64_t v = buf[cur][tid] + (tid >= off ? buf[cur][tid - off] : 0);
-        buf[cur ^ 1][tid] = v;
-        cur ^= 1;
-        __syncthreads();
+    int64_t before = 0, total = 0;
+#pragma unroll
+    for (int w = 0; w < 16; ++w) {
+        const int64_t x = wtot[w];
+        before += w < wave ? x : 0;
+        total += x;
     }
-    int64_t acc = buf[cur][tid] - run;   // exclusive prefix of this thread's entries
-    for (int64_t i = b; i < e; ++i) {
-        const int64_t c = wsum[i];
-        wsum[i] = acc;
-        acc += c;
+    int64_t acc = before + inc - run;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int64_t i = static_cast<int64_t>(tid) * kPer + k;
+        if (i < nw) wsum[i] = acc;
+        acc += v[k];
     }
-    if (tid == 1023) {
-        *split = buf[cur][1023];
+    if (tid == 0) {
+        *split = total;
         *err = 0;
     }
 }
@@ -223,7 +237,7 @@ __global__ __launch_bounds__((FlatCfg<MODE, VEC>::kBlock)) void flat_scan_kernel
         const int64_t nout = MODE == IXP_MODE_PARTITION ? nvalid : static_cast<int64_t>(tcount);
         for (int64_t s = tid; s < nout; s += kBlock) {
             const int64_t dst = s < tcount ? excl + s : false_base + (s - tcount);
-            if (dst < a.n) a.out_keys[dst] = stage[s];
+            if (dst < a.n) stream_store(a.out_keys + dst, stage[s]);
         }
     }
 }

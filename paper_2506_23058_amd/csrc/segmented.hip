@@ -1,0 +1,634 @@
+// segmented.hip -- partition2L / filter_seg on gfx950: partition2 applied to
+// every row of a jagged array given by its shape (Section 6, "Segmented
+// operations"; the flat-form helpers mkSgmDescr / mkII of Section 2.1).
+//
+// Row k covers [o_k, o_k + s_k), o_k = s_0 + ... + s_{k-1}.  Partition writes
+//   idx[i] = o_k + (c_i ? #trues before i in row k : T_k + #falses before i in row k)
+// (the index function the paper infers for partition2L); filter packs the kept
+// elements of all rows one row after the other (so a kept element goes to the
+// number of kept elements before it in the whole array) and gives -1 to the
+// others.  T_k (trues of row k) is written for every row, and optionally the
+// segment descriptor: a byte array with 1 at o_k for every non-empty row.
+//
+// Work decomposition.  Each non-empty row is cut into work items of at most
+// one tile (TILE = block * rows * 4 elements), aligned to 4-element groups so
+// that loads stay vector loads: item j of row k covers
+//   [A_k + j*TILE, A_k + (j+1)*TILE) ∩ [o_k, o_k + s_k),   A_k = o_k rounded down to 4.
+// Kernels (all stream-ordered, capturable in one HIP graph):
+//   seg_setup -- one workgroup: validates the shape, scans it into row offsets
+//                and item offsets, writes one descriptor per item, resets the
+//                work queue;
+//   seg_count -- one wave per item counts the trues of the items whose row
+//                spans several items (partition) or of every item (filter);
+//   seg_scan  -- per row (partition) / over all items (filter): turns item
+//                counts into output bases and writes T_k of multi-item rows;
+//   seg_main  -- persistent workgroups pull items from an atomic queue; each
+//                loads its item, ranks the trues by ballot/mbcnt, writes the
+//                indices and descriptor bytes in input order and the keys,
+//                staged in LDS, as two contiguous runs.  A row that fits one
+//                item is read once: its T_k comes from the item itself.
+#include "device.hpp"
+#include "host.hpp"
+
+namespace ixp {
+namespace {
+
+constexpr size_t kSegHeader = 256;   // ticket u32 @0, error i32 @4, item count i64 @8
+
+// Per-item descriptor written by seg_setup and completed by seg_scan.
+struct alignas(16) SegItem {
+    int64_t lo, hi;      // valid positions [lo, hi)
+    int64_t base;        // first position of the item's 4-aligned tile
+    int64_t tbase;       // output position of the item's first true
+    int64_t fbase;       // output position of the item's first false
+    int32_t row;         // row k
+    int32_t kind;        // bit 0: row fits one item; bit 1: first item of its row
+    int64_t count;       // trues in the item (counted items only)
+};
+
+struct SegArgs {
+    const uint32_t *keys;
+    int64_t n;
+    const int64_t *shape;
+    int64_t m;
+    uint32_t *out_keys;
+    void *out_idx;
+    int64_t *seg_split;
+    uint8_t *flags_out;
+    int64_t *offsets;     // [m + 1] row offsets
+    int64_t *item_off;    // [m + 1] first item of each row
+    SegItem *items;       // [max_items]
+    int64_t max_items;
+    uint32_t *ticket;
+    int32_t *err;
+    int64_t *num_items;
+    int64_t tile;
+    int32_t mode;
+    int32_t need_keys;
+};
+
+int64_t seg_max_items(int64_t n, int64_t m, int64_t tile) {
+    return ceil_div(n + 3 * m, tile) + m + 1;
+}
+
+// ------------------------------------------------------------------ setup --
+// One workgroup of 1024 threads.  Shapes are processed in chunks of 16384
+// rows (16 consecutive rows per thread); the per-thread sums of row sizes and
+// item counts are scanned with wave shuffles and LDS, carried across chunks.
+constexpr int kSetupThreads = 1024;
+constexpr int kSetupPer = 16;
+
+__device__ __forceinline__ int64_t block_exclusive_scan_1024(int64_t v, int64_t *lds16,
+                                                             int64_t *total) {
+    const int lane = threadIdx.x & 63;
+    const int wave = wave_id();
+    int64_t inc = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int64_t o = __shfl_up(inc, off, 64);
+        if (lane >= off) inc += o;
+    }
+    if (lane == 63) lds16[wave] = inc;
+    __syncthreads();
+    int64_t before = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < 16; ++w) {
+        const int64_t x = lds16[w];
+        before += w < wave ? x : 0;
+        tot += x;
+    }
+    __syncthreads();
+    *total = tot;
+    return before + inc - v;
+}
+
+__global__ __launch_bounds__(kSetupThreads) void seg_setup_kernel(SegArgs a) {
+    __shared__ int64_t lds_a[16], lds_b[16];
+    __shared__ int bad;
+    const int tid = threadIdx.x;
+    if (tid == 0) bad = 0;
+    __syncthreads();
+    int64_t carry_off = 0, carry_items = 0;
+    for (int64_t c0 = 0; c0 < a.m; c0 += static_cast<int64_t>(kSetupThreads) * kSetupPer) {
+        const int64_t r0 = c0 + static_cast<int64_t>(tid) * kSetupPer;
+        int64_t s[kSetupPer];
+        int64_t sum_s = 0;
+#pragma unroll
+        for (int j = 0; j < kSetupPer; ++j) {
+            const int64_t k = r0 + j;
+            s[j] = k < a.m ? a.shape[k] : 0;
+            if (s[j] < 0) atomicOr(&bad, 1);
+            sum_s += s[j] < 0 ? 0 : s[j];
+        }
+        int64_t tot_s;
+        const int64_t off0 = carry_off + block_exclusive_scan_1024(sum_s, lds_a, &tot_s);
+        // items per row depend on the row offset (4-alignment of its start)
+        int64_t nitems[kSetupPer];
+        int64_t sum_it = 0;
+        {
+            int64_t o = off0;
+#pragma unroll
+            for (int j = 0; j < kSetupPer; ++j) {
+                const int64_t sk = s[j] < 0 ? 0 : s[j];
+                const int64_t ak = o & ~int64_t{3};
+                nitems[j] = sk > 0 ? ceil_div(o + sk - ak, a.tile) : 0;
+                sum_it += nitems[j];
+                o += sk;
+            }
+        }
+        int64_t tot_it;
+        const int64_t it0 = carry_items + block_exclusive_scan_1024(sum_it, lds_b, &tot_it);
+        int64_t o = off0, it = it0;
+#pragma unroll
+        for (int j = 0; j < kSetupPer; ++j) {
+            const int64_t k = r0 + j;
+            if (k < a.m) {
+                a.offsets[k] = o;
+                a.item_off[k] = it;
+                const int64_t sk = s[j] < 0 ? 0 : s[j];
+                const int64_t ak = o & ~int64_t{3};
+                for (int64_t q = 0; q < nitems[j]; ++q) {
+                    const int64_t idx = it + q;
+                    if (idx < a.max_items) {
+                        SegItem d;
+                        d.base = ak + q * a.tile;
+                        d.lo = d.base > o ? d.base : o;
+                        d.hi = d.base + a.tile < o + sk ? d.base + a.tile : o + sk;
+                        d.tbase = 0;
+                        d.fbase = 0;
+                        d.row = static_cast<int32_t>(k);
+                        d.kind = (nitems[j] == 1 ? 1 : 0) | (q == 0 ? 2 : 0);
+                        d.count = 0;
+                        a.items[idx] = d;
+                    }
+                }
+            }
+            o += s[j] < 0 ? 0 : s[j];
+            it += nitems[j];
+        }
+        carry_off += tot_s;
+        carry_items += tot_it;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        const bool ok = !bad && carry_off == a.n && carry_items <= a.max_items;
+        a.offsets[a.m] = carry_off;
+        a.item_off[a.m] = carry_items;
+        *a.num_items = ok ? carry_items : 0;
+        *a.ticket = 0;
+        *a.err = ok ? 0 : kErrShape;
+    }
+}
+
+// ------------------------------------------------------------------ count --
+template <class Pred>
+__global__ __launch_bounds__(256) void seg_count_kernel(SegArgs a, Pred pred) {
+    using WT = Tile<kWave, 4, 4>;   // one wave, 1024 elements per chunk
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t nitems = *a.num_items;
+    const int64_t w0 = static_cast<int64_t>(blockIdx.x) * 4 + wave_id();
+    const int64_t nw = static_cast<int64_t>(gridDim.x) * 4;
+    for (int64_t it = w0; it < nitems; it += nw) {
+        const SegItem d = a.items[it];
+        if (a.mode == IXP_MODE_PARTITION && (d.kind & 1)) continue;   // counted in place
+        uint32_t cnt = 0;
+        for (int64_t b = d.base; b < d.hi; b += WT::kSize) {
+            WT chunk;
+            chunk.load(a.keys, a.n, b, d.lo, d.hi, pred, !Pred::kUsesFlags, 0, lane);
+            cnt += chunk.wave_count();
+        }
+        if (lane == 0) a.items[it].count = cnt;
+    }
+}
+
+// ------------------------------------------------------------------- scan --
+// Partition: one thread per row; rows of several items get their items'
+// output bases and T_k.
+__global__ __launch_bounds__(256) void seg_scan_rows_kernel(SegArgs a) {
+    const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= a.m || *a.err != 0) return;
+    const int64_t i0 = a.item_off[k], i1 = a.item_off[k + 1];
+    if (i1 == i0 && a.seg_split) a.seg_split[k] = 0;   // empty row
+    if (i1 - i0 <= 1) return;   // one-item rows are finished by the main kernel
+    const int64_t ok = a.offsets[k];
+    int64_t tk = 0;
+    for (int64_t i = i0; i < i1; ++i) tk += a.items[i].count;
+    int64_t before = 0;
+    for (int64_t i = i0; i < i1; ++i) {
+        const int64_t lo = a.items[i].lo;
+        a.items[i].tbase = ok + before;
+        a.items[i].fbase = ok + tk + (lo - ok - before);
+        before += a.items[i].count;
+    }
+    if (a.seg_split) a.seg_split[k] = tk;
+}
+
+// Filter: one workgroup scans all item counts (chunks of 1024 * 8 items) into
+// global output bases; then one thread per row sums its T_k.
+__global__ __launch_bounds__(1024) void seg_scan_items_kernel(SegArgs a) {
+    __shared__ int64_t lds[16];
+    const int64_t nitems = *a.num_items;
+    constexpr int kPer = 8;
+    int64_t carry = 0;
+    for (int64_t c0 = 0; c0 < nitems; c0 += 1024 * kPer) {
+        const int64_t i0 = c0 + static_cast<int64_t>(threadIdx.x) * kPer;
+        int64_t v[kPer];
+        int64_t sum = 0;
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            v[j] = i0 + j < nitems ? a.items[i0 + j].count : 0;
+            sum += v[j];
+        }
+        int64_t tot;
+        int64_t acc = carry + block_exclusive_scan_1024(sum, lds, &tot);
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            if (i0 + j < nitems) {
+                a.items[i0 + j].tbase = acc;
+                a.items[i0 + j].fbase = 0;
+            }
+            acc += v[j];
+        }
+        carry += tot;
+    }
+}
+
+__global__ __launch_bounds__(256) void seg_row_totals_kernel(SegArgs a) {
+    const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= a.m || *a.err != 0 || !a.seg_split) return;
+    int64_t tk = 0;
+    for (int64_t i = a.item_off[k]; i < a.item_off[k + 1]; ++i) tk += a.items[i].count;
+    a.seg_split[k] = tk;
+}
+
+// ------------------------------------------------------------------- main --
+template <int BLOCK, int ROWS, class Pred, int MODE, class Idx>
+__global__ __launch_bounds__(BLOCK) void seg_main_kernel(SegArgs a, Pred pred) {
+    using T = Tile<BLOCK, ROWS, 4>;
+    constexpr int kTile = T::kSize;
+    __shared__ uint32_t stage[kTile];
+    __shared__ uint32_t wtot[T::kWaves];
+    __shared__ int64_t sh_item;
+
+    const int tid = threadIdx.x;
+    const int wave = wave_id();
+    const int lane = tid & (kWave - 1);
+    const int64_t nitems = *a.num_items;
+    Idx *out_idx = static_cast<Idx *>(a.out_idx);
+
+    for (;;) {
+        if (tid == 0) sh_item = atomicAdd(a.ticket, 1u);
+        __syncthreads();
+        const int64_t it = sh_item;
+        if (it >= nitems) break;
+        const SegItem d = a.items[it];
+        const int64_t lo = d.lo, hi = d.hi, base = d.base;
+
+        T tile;
+        tile.load(a.keys, a.n, base, lo, hi, pred, a.need_keys != 0, wave, lane);
+        tile.wave_ranks();
+        const uint32_t tcount = tile.block_ranks(wtot, wave, lane);
+
+        int64_t tbase = d.tbase, fbase = d.fbase;
+        if (MODE == IXP_MODE_PARTITION && (d.kind & 1)) {
+            tbase = lo;
+            fbase = lo + tcount;
+            if (tid == 0 && a.seg_split) a.seg_split[d.row] = tcount;
+        }
+        const bool first = (d.kind & 2) != 0;
+
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r) {
+            const int64_t p0 = T::pos(base, wave, r, lane, 0);
+            Idx v[4];
+            uint32_t vm = 0;
+            uint32_t fl = 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint32_t rt = tile.rank[r][q];
+                const int64_t p = p0 + q;
+                const uint32_t rf = static_cast<uint32_t>(p - lo) - rt;
+                const bool f = tile.flag(r, q);
+                const bool ok = tile.valid(r, q);
+                vm |= static_cast<uint32_t>(ok) << q;
+                fl |= static_cast<uint32_t>(first && p == lo) << (8 * q);
+                if (MODE == IXP_MODE_PARTITION)
+                    v[q] = static_cast<Idx>(f ? tbase + rt : fbase + rf);
+                else
+                    v[q] = static_cast<Idx>(f ? tbase + rt : -1);
+                if (a.out_keys && ok && (MODE == IXP_MODE_PARTITION || f))
+                    stage[f ? rt : tcount + rf] = tile.key[r][q];
+            }
+            if (vm) {
+                if (out_idx) store_idx_group<4, Idx>(out_idx, p0, v, vm);
+                if (a.flags_out) {
+                    if (vm == 0xFu) {
+                        stream_store(reinterpret_cast<uint32_t *>(a.flags_out + p0), fl);
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+                            if ((vm >> q) & 1u)
+                                a.flags_out[p0 + q] = static_cast<uint8_t>(fl >> (8 * q));
+                    }
+                }
+            }
+        }
+        if (a.out_keys) {
+            __syncthreads();
+            const int64_t nvalid = hi - lo;
+            const int64_t nout = MODE == IXP_MODE_PARTITION ? nvalid : static_cast<int64_t>(tcount);
+            for (int64_t s = tid; s < nout; s += BLOCK) {
+                const int64_t dst = s < tcount ? tbase + s : fbase + (s - tcount);
+                if (dst >= 0 && dst < a.n) stream_store(a.out_keys + dst, stage[s]);
+            }
+        }
+        __syncthreads();   // LDS and sh_item are reused by the next item
+    }
+}
+
+// ----------------------------------------------------------------- launch --
+struct SegGeom {
+    int block, rows, wgs_per_cu;
+    int64_t tile() const { return static_cast<int64_t>(block) * rows * 4; }
+};
+
+bool geom_supported(const SegGeom &g) {
+    const bool b = g.block == 256 || g.block == 512 || g.block == 1024;
+    const bool r = g.rows == 2 || g.rows == 4 || g.rows == 8;
+    return b && r && g.tile() <= 16384 && g.wgs_per_cu >= 1 && g.wgs_per_cu <= 16;
+}
+
+SegGeom geom_from(const ixp_tuning *t) {
+    SegGeom g{512, 4, 3};
+    if (t) {
+        if (t->block) g.block = t->block;
+        if (t->rows) g.rows = t->rows;
+        g.wgs_per_cu = t->wgs_per_cu > 0 ? t->wgs_per_cu : 0;
+    }
+    if (g.wgs_per_cu == 0) {
+        // as many workgroups per CU as the LDS tile and 32 waves allow, at most 8
+        const int64_t by_lds = (160 * 1024) / (g.tile() * 4 + 1024);
+        const int64_t by_waves = 32 / (g.block / 64);
+        int64_t w = by_lds < by_waves ? by_lds : by_waves;
+        if (w > 8) w = 8;
+        g.wgs_per_cu = static_cast<int>(w < 1 ? 1 : w);
+    }
+    return g;
+}
+
+template <int BLOCK, int ROWS, class Pred>
+int launch_main_geom(const SegArgs &a, const Pred &p, int mode, int idx_t, int grid, hipStream_t st) {
+    if (mode == IXP_MODE_PARTITION) {
+        if (idx_t == IXP_I32)
+            IXP_LAUNCH("seg_main_partition", (seg_main_kernel<BLOCK, ROWS, Pred, IXP_MODE_PARTITION, int32_t>),
+                       dim3(grid), dim3(BLOCK), 0, st, a, p);
+        else
+            IXP_LAUNCH("seg_main_partition", (seg_main_kernel<BLOCK, ROWS, Pred, IXP_MODE_PARTITION, int64_t>),
+                       dim3(grid), dim3(BLOCK), 0, st, a, p);
+    } else {
+        if (idx_t == IXP_I32)
+            IXP_LAUNCH("seg_main_filter", (seg_main_kernel<BLOCK, ROWS, Pred, IXP_MODE_FILTER, int32_t>),
+                       dim3(grid), dim3(BLOCK), 0, st, a, p);
+        else
+            IXP_LAUNCH("seg_main_filter", (seg_main_kernel<BLOCK, ROWS, Pred, IXP_MODE_FILTER, int64_t>),
+                       dim3(grid), dim3(BLOCK), 0, st, a, p);
+    }
+    return launch_status();
+}
+
+template <class Pred>
+int launch_main(const SegArgs &a, const Pred &p, const SegGeom &g, int mode, int idx_t, hipStream_t st) {
+    const int grid = device_cus() * g.wgs_per_cu;
+#define IXP_SEG_GEOM(B, R) \
+    if (g.block == B && g.rows == R) return launch_main_geom<B, R, Pred>(a, p, mode, idx_t, grid, st);
+    IXP_SEG_GEOM(256, 2)
+    IXP_SEG_GEOM(256, 4)
+    IXP_SEG_GEOM(256, 8)
+    IXP_SEG_GEOM(512, 2)
+    IXP_SEG_GEOM(512, 4)
+    IXP_SEG_GEOM(512, 8)
+    IXP_SEG_GEOM(1024, 2)
+    IXP_SEG_GEOM(1024, 4)
+#undef IXP_SEG_GEOM
+    return IXP_EUNSUPPORTED;
+}
+
+template <class Pred>
+int launch_all(const SegArgs &a, const Pred &p, const SegGeom &g, int mode, int idx_t, hipStream_t st) {
+    IXP_LAUNCH("seg_setup", seg_setup_kernel, dim3(1), dim3(kSetupThreads), 0, st, a);
+    if (launch_status() != IXP_OK) return IXP_EHIP;
+    const int cus = device_cus();
+    IXP_LAUNCH("seg_count", (seg_count_kernel<Pred>), dim3(cus * 8), dim3(256), 0, st, a, p);
+    if (launch_status() != IXP_OK) return IXP_EHIP;
+    const uint32_t rblocks = static_cast<uint32_t>(ceil_div(a.m > 0 ? a.m : 1, 256));
+    if (mode == IXP_MODE_PARTITION) {
+        IXP_LAUNCH("seg_scan_rows", seg_scan_rows_kernel, dim3(rblocks), dim3(256), 0, st, a);
+    } else {
+        IXP_LAUNCH("seg_scan_items", seg_scan_items_kernel, dim3(1), dim3(1024), 0, st, a);
+        if (launch_status() != IXP_OK) return IXP_EHIP;
+        IXP_LAUNCH("seg_row_totals", seg_row_totals_kernel, dim3(rblocks), dim3(256), 0, st, a);
+    }
+    if (launch_status() != IXP_OK) return IXP_EHIP;
+    return launch_main(a, p, g, mode, idx_t, st);
+}
+
+size_t seg_workspace(int64_t n, int64_t m, const SegGeom &g) {
+    const int64_t mi = seg_max_items(n, m, g.tile());
+    return kSegHeader + round_up(static_cast<size_t>(m + 1) * 8, 256) * 2 +
+           static_cast<size_t>(mi) * sizeof(SegItem);
+}
+
+int prepare(const void *keys, int32_t key_t, int64_t n, const int64_t *d_shape, int64_t m,
+            const ixp_pred *pred, int32_t mode, void *out_keys, void *out_idx, int32_t idx_t,
+            int64_t *d_seg_split, uint8_t *d_flags_out, const SegGeom &g, void *ws,
+            size_t ws_bytes, SegArgs *a, HostPred *hp) {
+    if (n < 0 || m < 0 || (m > 0 && !d_shape)) return IXP_EINVAL;
+    if (m > 0x7FFFFFFFll) return IXP_EINVAL;
+    if (mode != IXP_MODE_PARTITION && mode != IXP_MODE_FILTER) return IXP_EINVAL;
+    if (idx_t != IXP_I32 && idx_t != IXP_I64) return IXP_EINVAL;
+    if (idx_t == IXP_I32 && n > 0x7FFFFFFFll) return IXP_EINVAL;
+    if (key_t != IXP_I32 && key_t != IXP_F32) return key_t == IXP_I64 ? IXP_EUNSUPPORTED : IXP_EINVAL;
+    if (!geom_supported(g)) return IXP_EINVAL;
+    int rc = check_pred(pred, key_t, hp);
+    if (rc != IXP_OK) return rc;
+    const bool need_keys = hp->kind != IXP_PRED_FLAGS || out_keys != nullptr;
+    if (n > 0 && need_keys && !keys) return IXP_EINVAL;
+    if (!ws || ws_bytes < seg_workspace(n, m, g)) return IXP_EWORKSPACE;
+    const size_t isz = idx_t == IXP_I32 ? 4 : 8;
+    // vector groups of 4 elements: keys, indices and flag bytes must be
+    // aligned to a whole group
+    if (!aligned(keys, 16) || !aligned(out_keys, 4) || !aligned(out_idx, 4 * isz) ||
+        !aligned(d_flags_out, 4) || !aligned(d_shape, 8) || !aligned(d_seg_split, 8) ||
+        !aligned(ws, 16))
+        return IXP_EINVAL;
+    if (hp->kind == IXP_PRED_FLAGS && !aligned(hp->flags, 4)) return IXP_EINVAL;
+    char *w = static_cast<char *>(ws);
+    const size_t rows_bytes = round_up(static_cast<size_t>(m + 1) * 8, 256);
+    a->keys = static_cast<const uint32_t *>(keys);
+    a->n = n;
+    a->shape = d_shape;
+    a->m = m;
+    a->out_keys = static_cast<uint32_t *>(out_keys);
+    a->out_idx = out_idx;
+    a->seg_split = d_seg_split;
+    a->flags_out = d_flags_out;
+    a->ticket = reinterpret_cast<uint32_t *>(w);
+    a->err = reinterpret_cast<int32_t *>(w + 4);
+    a->num_items = reinterpret_cast<int64_t *>(w + 8);
+    a->offsets = reinterpret_cast<int64_t *>(w + kSegHeader);
+    a->item_off = reinterpret_cast<int64_t *>(w + kSegHeader + rows_bytes);
+    a->items = reinterpret_cast<SegItem *>(w + kSegHeader + 2 * rows_bytes);
+    a->max_items = seg_max_items(n, m, g.tile());
+    a->tile = g.tile();
+    a->mode = mode;
+    a->need_keys = need_keys ? 1 : 0;
+    return IXP_OK;
+}
+
+int run(const SegArgs &a, const HostPred &hp, const SegGeom &g, int mode, int idx_t, hipStream_t st) {
+    switch (hp.kind) {
+    case IXP_PRED_MOD_EQ: return launch_all(a, PredModEq{hp.M, hp.d, hp.r}, g, mode, idx_t, st);
+    case IXP_PRED_LT: return launch_all(a, PredLt{hp.s}, g, mode, idx_t, st);
+    default: return launch_all(a, PredFlags{hp.flags}, g, mode, idx_t, st);
+    }
+}
+
+}  // namespace
+}  // namespace ixp
+
+using namespace ixp;
+
+struct ixp_graph_s {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+extern "C" size_t ixp_segmented_workspace(int64_t n, int64_t m, const ixp_tuning *tune) {
+    if (n < 0 || m < 0) return 0;
+    const SegGeom g = geom_from(tune);
+    if (!geom_supported(g)) return 0;
+    return seg_workspace(n, m, g);
+}
+
+extern "C" int ixp_segmented_partition(const void *keys, int32_t key_t, int64_t n,
+                                       const int64_t *d_shape, int64_t m, const ixp_pred *pred,
+                                       int32_t mode, void *out_keys, void *out_idx, int32_t idx_t,
+                                       int64_t *d_seg_split, uint8_t *d_flags_out,
+                                       const ixp_tuning *tune, void *ws, size_t ws_bytes,
+                                       void *stream) {
+    const SegGeom g = geom_from(tune);
+    SegArgs a;
+    HostPred hp;
+    int rc = prepare(keys, key_t, n, d_shape, m, pred, mode, out_keys, out_idx, idx_t, d_seg_split,
+                     d_flags_out, g, ws, ws_bytes, &a, &hp);
+    if (rc != IXP_OK) return rc;
+    return run(a, hp, g, mode, idx_t, as_stream(stream));
+}
+
+extern "C" int ixp_tune_segmented(const void *keys, int32_t key_t, int64_t n,
+                                  const int64_t *d_shape, int64_t m, const ixp_pred *pred,
+                                  int32_t mode, void *out_keys, void *out_idx, int32_t idx_t,
+                                  int64_t *d_seg_split, uint8_t *d_flags_out, void *ws,
+                                  size_t ws_bytes, int32_t reps, ixp_tuning *best, float *best_ms,
+                                  void *stream) {
+    if (!best) return IXP_EINVAL;
+    if (reps < 1) reps = 1;
+    hipStream_t st = as_stream(stream);
+    static const int kCands[][2] = {{256, 4}, {256, 8}, {512, 2}, {512, 4}, {512, 8},
+                                    {1024, 2}, {1024, 4}};
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return IXP_EHIP;
+    if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return IXP_EHIP; }
+    float best_t = -1.f;
+    int rc_out = IXP_EUNSUPPORTED;
+    for (const auto &c : kCands) {
+        for (int wpc = 0; wpc <= 1; ++wpc) {
+            ixp_tuning t{c[0], c[1], 0, 0};
+            SegGeom g = geom_from(&t);
+            if (wpc == 1) g.wgs_per_cu = g.wgs_per_cu > 1 ? g.wgs_per_cu - 1 : 1;
+            t.wgs_per_cu = g.wgs_per_cu;
+            SegArgs a;
+            HostPred hp;
+            if (prepare(keys, key_t, n, d_shape, m, pred, mode, out_keys, out_idx, idx_t, d_seg_split,
+                        d_flags_out, g, ws, ws_bytes, &a, &hp) != IXP_OK)
+                continue;
+            if (run(a, hp, g, mode, idx_t, st) != IXP_OK) continue;   // warm-up
+            (void)hipEventRecord(e0, st);
+            int rc = IXP_OK;
+            for (int r = 0; r < reps && rc == IXP_OK; ++r) rc = run(a, hp, g, mode, idx_t, st);
+            (void)hipEventRecord(e1, st);
+            if (rc != IXP_OK || hipEventSynchronize(e1) != hipSuccess) continue;
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            ms /= static_cast<float>(reps);
+            if (best_t < 0.f || ms < best_t) {
+                best_t = ms;
+                *best = t;
+                rc_out = IXP_OK;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (best_ms) *best_ms = best_t;
+    return rc_out;
+}
+
+extern "C" int ixp_segmented_graph_create(ixp_graph *out, const void *keys, int32_t key_t, int64_t n,
+                                          const int64_t *d_shape, int64_t m, const ixp_pred *pred,
+                                          int32_t mode, void *out_keys, void *out_idx,
+                                          int32_t idx_t, int64_t *d_seg_split,
+                                          uint8_t *d_flags_out, const ixp_tuning *tune, void *ws,
+                                          size_t ws_bytes) {
+    if (!out) return IXP_EINVAL;
+    *out = nullptr;
+    const SegGeom g = geom_from(tune);
+    SegArgs a;
+    HostPred hp;
+    int rc = prepare(keys, key_t, n, d_shape, m, pred, mode, out_keys, out_idx, idx_t, d_seg_split,
+                     d_flags_out, g, ws, ws_bytes, &a, &hp);
+    if (rc != IXP_OK) return rc;
+    (void)device_cus();   // cache the CU count outside the capture
+    hipStream_t cs = nullptr;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return IXP_EHIP;
+    auto *gr = new (std::nothrow) ixp_graph_s;
+    if (!gr) { (void)hipStreamDestroy(cs); return IXP_ENOMEM; }
+    rc = IXP_EHIP;
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+        const int lrc = run(a, hp, g, mode, idx_t, cs);
+        hipGraph_t graph = nullptr;
+        const hipError_t ec = hipStreamEndCapture(cs, &graph);
+        if (lrc == IXP_OK && ec == hipSuccess && graph) {
+            if (hipGraphInstantiate(&gr->exec, graph, nullptr, nullptr, 0) == hipSuccess) {
+                gr->graph = graph;
+                rc = IXP_OK;
+            } else {
+                (void)hipGraphDestroy(graph);
+            }
+        } else {
+            rc = lrc != IXP_OK ? lrc : IXP_EHIP;
+            if (graph) (void)hipGraphDestroy(graph);
+        }
+    }
+    (void)hipStreamDestroy(cs);
+    if (rc != IXP_OK) {
+        delete gr;
+        return rc;
+    }
+    *out = gr;
+    return IXP_OK;
+}
+
+extern "C" int ixp_graph_launch(ixp_graph g, void *stream) {
+    if (!g || !g->exec) return IXP_EINVAL;
+    return hipGraphLaunch(g->exec, as_stream(stream)) == hipSuccess ? IXP_OK : IXP_EHIP;
+}
+
+extern "C" int ixp_graph_destroy(ixp_graph g) {
+    if (!g) return IXP_EINVAL;
+    int rc = IXP_OK;
+    if (g->exec && hipGraphExecDestroy(g->exec) != hipSuccess) rc = IXP_EHIP;
+    if (g->graph && hipGraphDestroy(g->graph) != hipSuccess) rc = IXP_EHIP;
+    delete g;
+    return rc;
+}

@@ -128,3 +128,140 @@ def profile_read():
             "ixp_profile_read")
     return {buf[i].name.decode(): (int(buf[i].launches), float(buf[i].total_ms))
             for i in range(min(cnt.value, 64))}
+
+
+# ---------------------------------------------------------------- segmented --
+
+def _tuning(tune):
+    if tune is None:
+        return None
+    t = L.ixp_tuning()
+    t.block, t.rows, t.wgs_per_cu = int(tune[0]), int(tune[1]), int(tune[2]) if len(tune) > 2 else 0
+    return t
+
+
+def _seg_outputs(keys, shape, idx_dtype, want_flags, out_keys, out_idx, seg_split, flags):
+    n, m, dev = keys.numel(), shape.numel(), keys.device
+    if out_keys is None:
+        out_keys = torch.empty_like(keys)
+    if out_idx is None:
+        out_idx = torch.empty(n, dtype=idx_dtype, device=dev)
+    if seg_split is None:
+        seg_split = torch.empty(m, dtype=torch.int64, device=dev)
+    if want_flags and flags is None:
+        flags = torch.empty(n, dtype=torch.uint8, device=dev)
+    return out_keys, out_idx, seg_split, (flags if want_flags else None)
+
+
+def segmented_partition(keys: torch.Tensor, shape: torch.Tensor, pred: Pred,
+                        mode: int = L.MODE_PARTITION, idx_dtype=torch.int32,
+                        want_flags: bool = True, tune=None, out_keys=None, out_idx=None,
+                        seg_split=None, flags=None, ws_tag: str = "segmented"):
+    """partition2L / filter_seg: stable partition (or filter) of every row of
+    the jagged array whose row sizes are ``shape`` (int64, on the device).
+
+    Returns (out_keys, out_idx, seg_split, flags).  ``tune`` is a
+    (block, rows[, wgs_per_cu]) tuple, or None for the library default.
+    """
+    _check_dev(keys, shape)
+    keys = keys.contiguous()
+    shape = shape.contiguous()
+    if shape.dtype != torch.int64:
+        raise ValueError("shape must be int64")
+    out_keys, out_idx, seg_split, flags = _seg_outputs(keys, shape, idx_dtype, want_flags,
+                                                       out_keys, out_idx, seg_split, flags)
+    t = _tuning(tune)
+    tp = ctypes.byref(t) if t is not None else None
+    n, m = keys.numel(), shape.numel()
+    ws = workspace(L.lib().ixp_segmented_workspace(n, m, tp), keys.device, ws_tag)
+    pc = pred.c()
+    rc = L.lib().ixp_segmented_partition(
+        _ptr(keys), _KEY_T[keys.dtype], n, _ptr(shape), m, ctypes.byref(pc), mode,
+        _ptr(out_keys), _ptr(out_idx), _IDX_T[out_idx.dtype], _ptr(seg_split), _ptr(flags),
+        tp, _ptr(ws), ws.numel(), _stream_ptr(keys.device))
+    L.check(rc, "ixp_segmented_partition")
+    return out_keys, out_idx, seg_split, flags
+
+
+def segmented_error(ws_tag: str = "segmented", device="cuda:0") -> int:
+    """Blocking: status recorded by the last segmented call on this workspace
+    (IXP_EINVAL for an invalid shape array), then cleared."""
+    ws = _ws_cache.get((str(torch.device(device)), ws_tag))
+    if ws is None:
+        return L.IXP_OK
+    return L.lib().ixp_read_error(_ptr(ws), _stream_ptr(ws.device))
+
+
+def tune_segmented(keys, shape, pred, mode=L.MODE_PARTITION, idx_dtype=torch.int32,
+                   want_flags=True, reps: int = 5):
+    """Blocking autotuner: times every supported tiling on these arguments and
+    returns ((block, rows, wgs_per_cu), milliseconds)."""
+    keys = keys.contiguous()
+    shape = shape.contiguous()
+    out_keys, out_idx, seg_split, flags = _seg_outputs(keys, shape, idx_dtype, want_flags,
+                                                       None, None, None, None)
+    n, m = keys.numel(), shape.numel()
+    big = L.ixp_tuning()
+    big.block, big.rows = 256, 2     # smallest tile: largest workspace
+    ws = workspace(L.lib().ixp_segmented_workspace(n, m, ctypes.byref(big)), keys.device,
+                   "segmented_tune")
+    best = L.ixp_tuning()
+    ms = ctypes.c_float(0)
+    pc = pred.c()
+    rc = L.lib().ixp_tune_segmented(
+        _ptr(keys), _KEY_T[keys.dtype], n, _ptr(shape), m, ctypes.byref(pc), mode,
+        _ptr(out_keys), _ptr(out_idx), _IDX_T[idx_dtype], _ptr(seg_split), _ptr(flags),
+        _ptr(ws), ws.numel(), reps, ctypes.byref(best), ctypes.byref(ms),
+        _stream_ptr(keys.device))
+    L.check(rc, "ixp_tune_segmented")
+    return (best.block, best.rows, best.wgs_per_cu), ms.value
+
+
+class SegmentedGraph:
+    """One segmented partition captured into a HIP graph by the library
+    (ixp_segmented_graph_create); launch() replays it on the current stream with
+    the same buffers.  The input tensors may be refilled between launches."""
+
+    def __init__(self, keys, shape, pred, mode=L.MODE_PARTITION, idx_dtype=torch.int32,
+                 want_flags=True, tune=None):
+        _check_dev(keys, shape)
+        self.keys = keys.contiguous()
+        self.shape = shape.contiguous()
+        self.pred = pred          # keeps a flag tensor alive
+        (self.out_keys, self.out_idx, self.seg_split,
+         self.flags) = _seg_outputs(self.keys, self.shape, idx_dtype, want_flags,
+                                    None, None, None, None)
+        t = _tuning(tune)
+        tp = ctypes.byref(t) if t is not None else None
+        n, m = self.keys.numel(), self.shape.numel()
+        self.ws = torch.empty(max(L.lib().ixp_segmented_workspace(n, m, tp), 256),
+                              dtype=torch.uint8, device=self.keys.device)
+        pc = pred.c()
+        h = ctypes.c_void_p()
+        rc = L.lib().ixp_segmented_graph_create(
+            ctypes.byref(h), _ptr(self.keys), _KEY_T[self.keys.dtype], n, _ptr(self.shape), m,
+            ctypes.byref(pc), mode, _ptr(self.out_keys), _ptr(self.out_idx),
+            _IDX_T[idx_dtype], _ptr(self.seg_split), _ptr(self.flags), tp, _ptr(self.ws),
+            self.ws.numel())
+        L.check(rc, "ixp_segmented_graph_create")
+        self._h = h
+
+    def launch(self):
+        L.check(L.lib().ixp_graph_launch(self._h, _stream_ptr(self.keys.device)),
+                "ixp_graph_launch")
+        return self.out_keys, self.out_idx, self.seg_split, self.flags
+
+    def error(self) -> int:
+        return L.lib().ixp_read_error(_ptr(self.ws), _stream_ptr(self.ws.device))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            torch.cuda.synchronize(self.keys.device)
+            L.lib().ixp_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,145 @@
+"""GPU parity of the segmented partition (partition2L / filter_seg) with the
+CPU oracle, bit-exact: keys, indices, per-row split points and the segment
+descriptor bytes."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+import paper_2506_23058_amd as P  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def _preds(kind, **kw):
+    if kind == "mod":
+        return P.Pred.mod_eq(kw["d"], kw["r"]), O.Pred.mod_eq(kw["d"], kw["r"])
+    if kind == "lt":
+        return P.Pred.lt(kw["s"]), O.Pred.lt(kw["s"])
+    flags = kw["flags"]
+    return P.Pred.from_flags(torch.from_numpy(flags).to(DEV)), O.Pred.from_flags(flags)
+
+
+def run_both(keys, shape, kind="mod", mode=0, idx_dtype=torch.int32, tune=None, **kw):
+    if not kw:
+        kw = {"d": 3, "r": 0}
+    gp, op = _preds(kind, **kw)
+    print(f"[seg] n={len(keys)} m={len(shape)} pred={kind} mode={mode} tune={tune}", flush=True)
+    kt = torch.from_numpy(keys).to(DEV)
+    st = torch.from_numpy(np.asarray(shape, dtype=np.int64)).to(DEV)
+    ok, oi, ss, fl = P.segmented_partition(kt, st, gp, mode=mode, idx_dtype=idx_dtype, tune=tune)
+    torch.cuda.synchronize()
+    assert P.segmented_error() == 0
+    ys, idx, seg, flags = O.partition2L(keys, np.asarray(shape, dtype=np.int64), op, mode)
+    gi = oi.cpu().numpy().astype(np.int64)
+    assert np.array_equal(gi, idx), f"idx differs first at {np.argmax(gi != idx)}"
+    assert np.array_equal(ss.cpu().numpy(), seg)
+    assert np.array_equal(fl.cpu().numpy(), flags)
+    nout = len(keys) if mode == P.MODE_PARTITION else int(seg.sum())
+    gk = ok.cpu().numpy()[:nout]
+    assert np.array_equal(gk.view(np.uint32), ys[:nout].view(np.uint32))
+    return gk, gi, ss.cpu().numpy()
+
+
+def test_paper_shape_example():
+    # the jagged shape of the paper's mkSgmDescr / mkII example
+    shape = [0, 2, 1, 0, 3]
+    keys = np.array([3, 4, 9, 5, 6, 7], dtype=np.int32)
+    gk, gi, ss = run_both(keys, shape)
+    # row 1 = [3,4] -> trues (x%3==0) first: [3,4]; row 2 = [9]; row 4 = [5,6,7] -> [6,5,7]
+    assert gk.tolist() == [3, 4, 9, 6, 5, 7]
+    assert ss.tolist() == [0, 1, 1, 0, 1]
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("idx_dtype", [torch.int32, torch.int64])
+def test_random_shapes_with_empty_rows(mode, idx_dtype):
+    for seed, (m, med, sig, empty) in enumerate([(1, 3, 0, 0), (17, 4, 2, 0.3), (300, 8, 2, 0.2),
+                                                 (2000, 6, 1.5, 0.5), (40, 13, 1.5, 0.1)]):
+        shape = W.segment_sizes(m, 200 + seed, median_log2=med, sigma_log2=sig, empty_frac=empty)
+        keys = W.int_keys(int(shape.sum()), 300 + seed)
+        run_both(keys, shape, mode=mode, idx_dtype=idx_dtype)
+
+
+@pytest.mark.parametrize("tune", [(256, 2), (256, 4), (256, 8), (512, 2), (512, 4), (512, 8),
+                                  (1024, 2), (1024, 4), (512, 4, 1)])
+def test_every_tiling_matches(tune):
+    shape = W.segment_sizes(400, 11, median_log2=11, sigma_log2=2.0, empty_frac=0.1)
+    keys = W.int_keys(int(shape.sum()), 12)
+    run_both(keys, shape, tune=tune)
+    run_both(keys, shape, mode=1, tune=tune)
+
+
+def test_rows_spanning_many_items_and_unaligned_starts():
+    shape = np.array([1, 3, 70_001, 2, 5, 0, 130_003, 1, 0, 4097, 4095, 16385], dtype=np.int64)
+    keys = W.int_keys(int(shape.sum()), 5)
+    run_both(keys, shape)
+    run_both(keys, shape, mode=1)
+    f = W.f32_uniform(int(shape.sum()), 6)
+    run_both(f, shape, kind="lt", s=0.3)
+    flags = (W.int_keys(int(shape.sum()), 7) % 5 == 0).astype(np.uint8)
+    run_both(keys, shape, kind="flags", flags=flags)
+
+
+def test_degenerate_shapes():
+    run_both(np.zeros(0, np.int32), [])
+    run_both(np.zeros(0, np.int32), [0, 0, 0])
+    run_both(np.arange(7, dtype=np.int32), [7])
+    run_both(np.arange(9, dtype=np.int32), [0, 0, 9, 0])
+    # n not a multiple of 4 at the array end
+    keys = W.int_keys(10_007, 3)
+    run_both(keys, [5000, 5007])
+
+
+def test_invalid_shape_reported_on_device_and_outputs_untouched():
+    keys = torch.arange(10, dtype=torch.int32, device=DEV)
+    out_idx = torch.full((10,), 77, dtype=torch.int32, device=DEV)
+    for bad in ([5, -1, 6], [3, 3], [4, 4, 4]):
+        shape = torch.tensor(bad, dtype=torch.int64, device=DEV)
+        P.segmented_partition(keys, shape, P.Pred.mod_eq(2, 0), out_idx=out_idx)
+        assert P.segmented_error() == P._lib.IXP_EINVAL
+        assert (out_idx == 77).all()
+    assert P.segmented_error() == 0
+
+
+def test_config_segmented_full_compare():
+    """10^4 rows, log-normal sizes (median 2^12, sigma 1.5 in log2), int32 keys,
+    key % 3 == 0, with the descriptor flag array."""
+    shape = W.segment_sizes(W.SEG_M, W.SEG_SIZES_SEED)
+    keys = W.int_keys(int(shape.sum()), W.SEG_KEYS_SEED)
+    run_both(keys, shape)
+    shape_e = W.segment_sizes(W.SEG_M, W.SEG_SIZES_SEED, empty_frac=0.1)
+    run_both(keys[: int(shape_e.sum())].copy(), shape_e, mode=0)
+
+
+def test_graph_replays_match_eager():
+    shape = W.segment_sizes(500, 21, median_log2=10, sigma_log2=1.5, empty_frac=0.1)
+    n = int(shape.sum())
+    k1 = torch.from_numpy(W.int_keys(n, 22)).to(DEV)
+    st = torch.from_numpy(shape).to(DEV)
+    g = P.SegmentedGraph(k1, st, P.Pred.mod_eq(3, 0))
+    for rep in range(4):
+        # refill the captured input in place, then replay
+        g.keys.copy_(torch.from_numpy(W.int_keys(n, 30 + rep)).to(DEV))
+        ok, oi, ss, fl = [t.clone() for t in g.launch()]
+        torch.cuda.synchronize()
+        ek, ei, es, ef = P.segmented_partition(g.keys, st, P.Pred.mod_eq(3, 0))
+        torch.cuda.synchronize()
+        assert torch.equal(ok, ek) and torch.equal(oi, ei)
+        assert torch.equal(ss, es) and torch.equal(fl, ef)
+        assert g.error() == 0
+    g.close()
+
+
+def test_autotuner_returns_a_valid_tiling():
+    shape = W.segment_sizes(1000, 41, median_log2=10, sigma_log2=1.5)
+    keys = W.int_keys(int(shape.sum()), 42)
+    kt = torch.from_numpy(keys).to(DEV)
+    st = torch.from_numpy(shape).to(DEV)
+    best, ms = P.tune_segmented(kt, st, P.Pred.mod_eq(3, 0), reps=2)
+    assert best[0] in (256, 512, 1024) and best[1] in (2, 4, 8) and ms > 0
+    run_both(keys, shape, tune=best)
