@@ -235,7 +235,9 @@ def check_bij(X, lo, hi, ilo, ihi):
 
 def check_filtpart(X, p: Pred, mode, Y, Z, split):
     X = np.ascontiguousarray(X)
-    Y = np.ascontiguousarray(Y, dtype=X.dtype)
+    Yn = np.zeros(len(X), dtype=X.dtype)       # Y is read at positions < n only
+    Yn[: min(len(Y), len(X))] = np.asarray(Y, dtype=X.dtype)[: len(X)]
+    Y = Yn
     Z = np.ascontiguousarray(Z, dtype=np.int64)
     v = np.zeros(3, dtype=np.int64)
     _check(_load().ixo_check_filtpart(_ptr(X), _key_t(X), len(X), *_pred_args(p),

@@ -494,7 +494,8 @@ int ixo_check_bij(const int64_t *X, int64_t n, int64_t lo, int64_t hi,
 /* ------------------------------------------------------------------------ */
 /* FiltPart check on the outputs of a flat partition (Section 2.3: FiltPart */
 /* and InvFiltPart; partition2's postcondition, Section 2.1).                */
-/* Inputs: X (the partitioned keys), the predicate, Y (the output keys), Z   */
+/* Inputs: X (the partitioned keys), the predicate, Y (the output keys, n    */
+/* entries; in FILTER mode only the first split are compared), Z             */
 /* (the scatter indices) and split.  Sub-checks, numbered as the bits of     */
 /* aux:                                                                      */
 /*   bit 0  Equiv: split == number of elements satisfying p^f-and-p^p        */
@@ -556,7 +557,7 @@ int ixo_check_filtpart(const void *X, int key_t, int64_t n, int pred_kind,
             if (has_last[cls] && !(z > last[cls])) bad |= 8;
             has_last[cls] = 1;
             last[cls] = z;
-            if (0 <= z && z < ylen &&
+            if (0 <= z && z < ylen && z < n &&
                 memcmp((const char *)Y + z * kb, (const char *)X + i * kb,
                        (size_t)kb) != 0)
                 bad |= 16;
