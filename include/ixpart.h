@@ -212,7 +212,8 @@ enum { IXP_MONO_LE = 0, IXP_MONO_LT = 1, IXP_MONO_GE = 2, IXP_MONO_GT = 3 };
  *          [img_lo,img_hi) (aux = X[i]); failing only on the count:
  *          first_violation = n, aux = least value of Img not attained.
  *   FILTPART: X = the partitioned keys (fp_src, key type fp_key_t), Y =
- *          fp_dst, Z = x (the index array), split = *fp_split (device int64),
+ *          fp_dst (n entries, as ixp_partition writes them; FILTER compares
+ *          the first split), Z = x (the index array), split = *fp_split,
  *          pred / mode as given to ixp_partition.  aux = OR of failing
  *          sub-checks: 1 split != #trues (#kept); 2 Z not a bijection onto
  *          [0,n) (FILTER: kept Z not injective into [0,split), or a dropped
@@ -245,7 +246,8 @@ size_t ixp_check_props_workspace(int64_t n, uint32_t mask,
                                  const ixp_prop_args *a);
 
 /* Checks the properties selected by `mask` (IXP_* bits) on the device array
- * x[0..n) of type x_t (IXP_I32 or IXP_I64) and writes d_out[b] for every bit b
+ * x[0..n) of type x_t (IXP_I32 or IXP_I64; x 16-byte aligned, the workspace
+ * 256-byte aligned) and writes d_out[b] for every bit b
  * in 0..4 (unselected properties get holds = 1, first_violation = -1).
  * Verdicts are deterministic: independent of scheduling and bit-exact with
  * the definitions above. */

@@ -4,5 +4,6 @@ kernels behind the C ABI of include/ixpart.h."""
 from ._lib import (MODE_FILTER, MODE_PARTITION, PRED_FLAGS, PRED_LT, PRED_MOD_EQ,  # noqa: F401
                    RANGE, MONO, INJ, BIJ, FILTPART, MONO_LE, MONO_LT, MONO_GE, MONO_GT,
                    IxpError, lib)
-from .ops import (Pred, SegmentedGraph, partition, profile_enable, profile_read,  # noqa: F401
-                  read_error, segmented_error, segmented_partition, tune_segmented, workspace)
+from .ops import (FiltPartArgs, Pred, SegmentedGraph, check_props, partition,  # noqa: F401
+                  profile_enable, profile_read, read_error, segmented_error,
+                  segmented_partition, tune_segmented, verdicts, workspace)

@@ -265,3 +265,50 @@ class SegmentedGraph:
             self.close()
         except Exception:
             pass
+
+
+# ------------------------------------------------------------- properties --
+
+@dataclass
+class FiltPartArgs:
+    """Outputs of a flat partition to check with FILTPART: the partitioned keys
+    ``src``, the output keys ``dst``, the predicate, the mode and the split
+    point (a 1-element int64 device tensor)."""
+    src: torch.Tensor
+    dst: torch.Tensor
+    pred: Pred
+    split: torch.Tensor
+    mode: int = L.MODE_PARTITION
+
+
+def check_props(x: torch.Tensor, mask: int, lo: int = 0, hi: int = 0, img_lo: int = 0,
+                img_hi: int = 0, mono_op: int = L.MONO_LE, fp: Optional[FiltPartArgs] = None):
+    """Run-time property checks (Range, Monotonic, Inj, Bij, FiltPart) of an
+    int32/int64 device array.  Returns a [5, 3] int64 device tensor of
+    (holds, first_violation, aux) per property, in the order of the IXP_*
+    bits; unselected properties read (1, -1, 0)."""
+    _check_dev(x)
+    x = x.contiguous()
+    n = x.numel()
+    a = L.ixp_prop_args()
+    a.lo, a.hi, a.img_lo, a.img_hi, a.mono_op = int(lo), int(hi), int(img_lo), int(img_hi), int(mono_op)
+    if fp is not None:
+        a.fp_mode = fp.mode
+        a.fp_src = fp.src.data_ptr()
+        a.fp_dst = fp.dst.data_ptr()
+        a.fp_key_t = _KEY_T[fp.src.dtype]
+        a.fp_pred = fp.pred.c()
+        a.fp_split = fp.split.data_ptr()
+    out = torch.empty(5 * 3, dtype=torch.int64, device=x.device)
+    ws = workspace(L.lib().ixp_check_props_workspace(n, mask, ctypes.byref(a)), x.device, "props")
+    rc = L.lib().ixp_check_props(_ptr(x), _IDX_T[x.dtype], n, mask, ctypes.byref(a), _ptr(out),
+                                 _ptr(ws), ws.numel(), _stream_ptr(x.device))
+    L.check(rc, "ixp_check_props")
+    v = out.view(5, 3).clone()
+    v[:, 0] = v[:, 0] & 0xFFFFFFFF   # holds is the low 32 bits of the first word
+    return v
+
+
+def verdicts(v: torch.Tensor):
+    """[(holds, first_violation, aux)] * 5 on the host (synchronises)."""
+    return [tuple(int(t) for t in row) for row in v.cpu().tolist()]
