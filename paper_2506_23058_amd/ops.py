@@ -312,3 +312,71 @@ def check_props(x: torch.Tensor, mask: int, lo: int = 0, hi: int = 0, img_lo: in
 def verdicts(v: torch.Tensor):
     """[(holds, first_violation, aux)] * 5 on the host (synchronises)."""
     return [tuple(int(t) for t in row) for row in v.cpu().tolist()]
+
+
+# ---------------------------------------------------------- rows / autograd --
+
+def scatter_inj(dst: torch.Tensor, idx: torch.Tensor, vals: torch.Tensor) -> torch.Tensor:
+    """dst[idx[i]] = vals[i] on rows (first axis), in place; out-of-range
+    indices are ignored.  ``idx`` must be injective on [0, len(dst))."""
+    _check_dev(dst, idx, vals)
+    vals = vals.contiguous()
+    idx = idx.contiguous()
+    if not dst.is_contiguous() or dst.dtype != vals.dtype or dst.shape[1:] != vals.shape[1:]:
+        raise ValueError("dst must be contiguous with the row shape and dtype of vals")
+    rb = vals.element_size()
+    for d in vals.shape[1:]:
+        rb *= d
+    rc = L.lib().ixp_scatter_inj(_ptr(dst), dst.shape[0], _ptr(idx), _IDX_T[idx.dtype], _ptr(vals),
+                                 vals.shape[0], rb, _stream_ptr(dst.device))
+    L.check(rc, "ixp_scatter_inj")
+    return dst
+
+
+def gather(src: torch.Tensor, idx: torch.Tensor, err: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """out[i] = src[idx[i]] on rows; an index outside [0, len(src)) gives a zero
+    row (and sets err[0] = 1 when an int32 error tensor is given)."""
+    _check_dev(src, idx)
+    src = src.contiguous()
+    idx = idx.contiguous()
+    out = torch.empty((idx.shape[0],) + tuple(src.shape[1:]), dtype=src.dtype, device=src.device)
+    rb = src.element_size()
+    for d in src.shape[1:]:
+        rb *= d
+    rc = L.lib().ixp_gather(_ptr(out), _ptr(src), src.shape[0], _ptr(idx), _IDX_T[idx.dtype],
+                            idx.shape[0], rb, _ptr(err), _stream_ptr(src.device))
+    L.check(rc, "ixp_gather")
+    return out
+
+
+class PartitionScatter(torch.autograd.Function):
+    """Differentiable partition of a payload carried by its keys.
+
+    forward(keys, payload, pred, mode): the partition2 indices of ``keys``
+    (int64, from the HIP partition) move every payload row to its partitioned
+    position with the atomic-free row scatter; returns
+    (y, partitioned keys, indices, split).  In FILTER mode y holds the kept rows
+    first (its remaining rows are zero).
+    backward: the indices are a bijection onto [0, n) (PARTITION) or an
+    injection into [0, split) (FILTER), so the gradient of a row is the
+    upstream gradient at its destination -- one row gather; dropped rows (index
+    -1) get zero.
+    """
+
+    @staticmethod
+    def forward(ctx, keys, payload, pred, mode=L.MODE_PARTITION):
+        ok, idx, split = partition(keys, pred, mode, torch.int64)
+        y = torch.zeros_like(payload) if mode == L.MODE_FILTER else torch.empty_like(payload)
+        scatter_inj(y, idx, payload)
+        ctx.save_for_backward(idx)
+        ctx.mark_non_differentiable(ok, idx, split)
+        return y, ok, idx, split
+
+    @staticmethod
+    def backward(ctx, gy, *unused):
+        (idx,) = ctx.saved_tensors
+        return None, gather(gy, idx), None, None
+
+
+def partition_scatter(keys, payload, pred, mode=L.MODE_PARTITION):
+    return PartitionScatter.apply(keys, payload, pred, mode)
