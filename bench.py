@@ -120,16 +120,16 @@ def main():
     prof = P.profile_read()
 
     kern = {k: {"launches": v[0], "avg_ms": v[1] / max(v[0], 1)} for k, v in prof.items()}
-    scan = kern.get("flat_scan_partition", {"avg_ms": float("nan")})
+    scan = kern.get("flat_scatter_partition", {"avg_ms": float("nan")})
     count = kern.get("flat_count", {"avg_ms": float("nan")})
     scan_alg = n * (4 + 4 + 4)            # read keys, write idx, write keys
     count_alg = n * 4                     # read keys
     achieved = scan_alg / (scan["avg_ms"] * 1e-3) / 1e9
-    for k, alg in (("flat_scan_partition", scan_alg), ("flat_count", count_alg)):
+    for k, alg in (("flat_scatter_partition", scan_alg), ("flat_count", count_alg)):
         if k in kern:
             kern[k]["alg_bytes_per_launch"] = alg
             kern[k]["alg_GBps"] = alg / (kern[k]["avg_ms"] * 1e-3) / 1e9
-    traffic = _traffic("flat_scan_partition", n)
+    traffic = _traffic("flat_scatter_partition", n)
     out = {
         "metric": "partitioned GElem/s + % HBM peak (flat, segmented, fwd+bwd) on 1 MI355X",
         "value": len(sels) * n / dt / 1e9,
@@ -147,7 +147,7 @@ def main():
                                "s in {0.01,0.5,0.99} (one partition each per step), int32 "
                                "positions + partitioned values + split",
                    "n": n, "selectivities": list(sels), "idx_dtype": "int32"},
-        "roofline": {"bound": "hbm", "kernel": "flat_scan_partition",
+        "roofline": {"bound": "hbm", "kernel": "flat_scatter_partition",
                      "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
                      "alg_bytes_per_launch": scan_alg},
@@ -168,6 +168,10 @@ def main():
     print(json.dumps(out))
 
 
+def _prof(P):
+    return {k: {"launches": v[0], "avg_ms": v[1] / max(v[0], 1)} for k, v in P.profile_read().items()}
+
+
 def sections(args, torch, np, P, W, dev, x, out_keys, out_idx, split):
     res = {}
     n = x.numel()
@@ -177,7 +181,7 @@ def sections(args, torch, np, P, W, dev, x, out_keys, out_idx, split):
     t = timed(lambda: y.copy_(x), steps, 2, torch)
     res["copy_reference"] = {"bytes": 2 * 4 * n, "ms": t * 1e3, "GBps": 8 * n / t / 1e9}
     del y
-    # filter mode (single pass) on the same input
+    # filter mode (single pass with decoupled look-back) on the same input
     fl = {}
     for s in W.FLAT_LARGE_SELECTIVITIES:
         p = P.Pred.lt(s)
@@ -186,7 +190,7 @@ def sections(args, torch, np, P, W, dev, x, out_keys, out_idx, split):
         T = int(split.item())
         alg = n * 4 + n * 4 + T * 4
         fl[str(s)] = {"ms": t * 1e3, "GElem_s": n / t / 1e9, "alg_GBps": alg / t / 1e9}
-    res["flat_filter_2^28"] = fl
+    res["flat_filter_2^28_f32"] = fl
     # small flat config: n = 2^20 int32 keys, key % 2 == 0, int64 indices
     ks = torch.from_numpy(W.int_keys(W.FLAT_SMALL_N, W.FLAT_SMALL_SEED)).to(dev)
     p = P.Pred.mod_eq(2, 0)
@@ -194,8 +198,146 @@ def sections(args, torch, np, P, W, dev, x, out_keys, out_idx, split):
     ois = torch.empty(ks.numel(), dtype=torch.int64, device=dev)
     t = timed(lambda: P.partition(ks, p, P.MODE_PARTITION, torch.int64, out_keys=oks,
                                   out_idx=ois, split=split), steps * 10, 5, torch)
-    res["flat_small_2^20_int64idx"] = {"ms": t * 1e3, "GElem_s": ks.numel() / t / 1e9}
+    res["flat_partition_2^20_int32_int64idx"] = {"ms": t * 1e3, "GElem_s": ks.numel() / t / 1e9,
+                                                 "alg_GBps": ks.numel() * 16 / t / 1e9}
+    del ks, oks, ois
+    res["segmented_10^4_rows"] = section_segmented(args, torch, np, P, W, dev)
+    res["fwd_bwd_2^24x16"] = section_autograd(args, torch, np, P, W, dev)
+    res["check_props_2^28_int64"] = section_props(args, torch, np, P, W, dev)
     return res
+
+
+def section_segmented(args, torch, np, P, W, dev):
+    """10^4 rows, log-normal sizes (median 2^12, sigma 1.5 in log2), int32 keys,
+    key % 3 == 0; int32 indices, int64 per-row splits, u8 descriptor."""
+    shape_np = W.segment_sizes(W.SEG_M, W.SEG_SIZES_SEED)
+    n = int(shape_np.sum())
+    keys = torch.from_numpy(W.int_keys(n, W.SEG_KEYS_SEED)).to(dev)
+    shape = torch.from_numpy(shape_np).to(dev)
+    pred = P.Pred.mod_eq(3, 0)
+    tiling, tune_ms, cached = P.autotuned_tiling(keys, shape, pred)
+    g = P.SegmentedGraph(keys, shape, pred, tune=tiling)
+    steps = max(5, args.steps)
+    t_graph = timed(g.launch, steps, 2, torch)
+    t_eager = timed(lambda: P.segmented_partition(keys, shape, pred, tune=tiling,
+                                                  out_keys=g.out_keys, out_idx=g.out_idx,
+                                                  seg_split=g.seg_split, flags=g.flags),
+                    steps, 2, torch)
+    P.profile_enable(True)
+    for _ in range(3):
+        P.segmented_partition(keys, shape, pred, tune=tiling, out_keys=g.out_keys,
+                              out_idx=g.out_idx, seg_split=g.seg_split, flags=g.flags)
+    torch.cuda.synchronize()
+    P.profile_enable(False)
+    kern = _prof(P)
+    # the plain per-call form: one flat partition per row (row-local indices,
+    # no descriptor), 10^4 host calls on the same stream
+    offs = np.concatenate([[0], np.cumsum(shape_np)])
+    ok = torch.empty_like(keys)
+    oi = torch.empty(n, dtype=torch.int32, device=dev)
+    sp = torch.empty(W.SEG_M, dtype=torch.int64, device=dev)
+
+    def per_call():
+        for k in range(W.SEG_M):
+            lo, hi = int(offs[k]), int(offs[k + 1])
+            if hi > lo:
+                P.partition(keys[lo:hi], pred, P.MODE_PARTITION, torch.int32,
+                            out_keys=ok[lo:hi], out_idx=oi[lo:hi], split=sp[k:k + 1])
+    t_calls = timed(per_call, 2, 1, torch)
+    g.close()
+    alg = n * (4 + 4 + 4 + 1) + W.SEG_M * 16
+    return {"n": n, "m": W.SEG_M, "tiling": {"block": tiling[0], "rows": tiling[1],
+                                             "wgs_per_cu": tiling[2]},
+            "tuner_ms": tune_ms, "tiling_from_cache": cached,
+            "graph_ms": t_graph * 1e3, "graph_GElem_s": n / t_graph / 1e9,
+            "graph_alg_GBps": alg / t_graph / 1e9, "graph_frac_of_8TBps": alg / t_graph / 8e12,
+            "eager_ms": t_eager * 1e3, "per_call_10^4_ms": t_calls * 1e3,
+            "speedup_vs_per_call": t_calls / t_graph, "alg_bytes": alg, "kernels": kern}
+
+
+def section_autograd(args, torch, np, P, W, dev):
+    """Differentiable partition: int32 keys n = 2^24, key % 2 == 0, payload f32
+    [n, 16] ~ N(0,1); one step = forward (partition + row scatter) + backward
+    (row gather)."""
+    n, cols = W.AUTOGRAD_N, W.AUTOGRAD_ROW
+    keys = torch.from_numpy(W.int_keys(n, W.AUTOGRAD_SEEDS[0])).to(dev)
+    payload = torch.from_numpy(W.f32_normal((n, cols), W.AUTOGRAD_SEEDS[1])).to(dev)
+    gy = torch.from_numpy(W.f32_normal((n, cols), W.AUTOGRAD_SEEDS[2])).to(dev)
+    pred = P.Pred.mod_eq(2, 0)
+    steps = max(5, args.steps)
+    p = payload.clone().requires_grad_(True)
+
+    def ours():
+        p.grad = None
+        y, _, _, _ = P.partition_scatter(keys, p, pred)
+        y.backward(gy)
+
+    t_ours = timed(ours, steps, 2, torch)
+    P.profile_enable(True)
+    for _ in range(3):
+        ours()
+    torch.cuda.synchronize()
+    P.profile_enable(False)
+    kern = _prof(P)
+
+    def per_call():
+        _, idx, _ = P.partition(keys, pred, P.MODE_PARTITION, torch.int64, want_keys=False)
+        y = torch.empty_like(payload).index_copy_(0, idx, payload)
+        gp = gy.index_select(0, idx)
+        return y, gp
+
+    t_plain = timed(per_call, steps, 2, torch)
+    q = payload.clone().requires_grad_(True)
+    ar = torch.arange(n, device=dev)
+
+    def torch_autograd():
+        q.grad = None
+        _, idx, _ = P.partition(keys, pred, P.MODE_PARTITION, torch.int64, want_keys=False)
+        inv = torch.empty_like(idx)
+        inv[idx] = ar
+        y = q.index_select(0, inv)
+        y.backward(gy)
+
+    t_ta = timed(torch_autograd, steps, 2, torch)
+    row = cols * 4
+    alg = n * (4 + 8) + n * (8 + row + row) + n * (8 + row + row)   # partition + fwd + bwd
+    return {"n": n, "row_bytes": row, "ours_ms": t_ours * 1e3, "ours_alg_GBps": alg / t_ours / 1e9,
+            "ours_frac_of_8TBps": alg / t_ours / 8e12,
+            "per_call_index_copy_select_ms": t_plain * 1e3,
+            "torch_autograd_index_select_ms": t_ta * 1e3,
+            "speedup_vs_per_call": t_plain / t_ours, "speedup_vs_torch_autograd": t_ta / t_ours,
+            "alg_bytes": alg, "kernels": kern}
+
+
+def section_props(args, torch, np, P, W, dev):
+    """int64 n = 2^28: Range+Inj+Bij on a permutation, Mono on a sorted array,
+    all four on the permutation with 1000 planted faults."""
+    n = W.PROPS_N
+    perm_np = W.permutation(n, W.PROPS_PERM_SEED)
+    perm = torch.from_numpy(perm_np).to(dev)
+    steps = max(3, args.steps // 2)
+    out = {}
+    m3 = P.RANGE | P.INJ | P.BIJ
+    t = timed(lambda: P.check_props(perm, m3, 0, n, 0, n), steps, 1, torch)
+    out["perm_range_inj_bij"] = {"ms": t * 1e3, "GElem_s": n / t / 1e9, "alg_GBps": 8 * n / t / 1e9,
+                                 "verdicts": P.verdicts(P.check_props(perm, m3, 0, n, 0, n))[:4]}
+    P.profile_enable(True)
+    P.check_props(perm, m3, 0, n, 0, n)
+    torch.cuda.synchronize()
+    P.profile_enable(False)
+    out["perm_kernels"] = _prof(P)
+    bad = torch.from_numpy(W.inject_faults(perm_np, 1000, 1052, "mixed")).to(dev)
+    del perm_np
+    m4 = m3 | P.MONO
+    t = timed(lambda: P.check_props(bad, m4, 0, n, 0, n), steps, 1, torch)
+    out["faulty_all4"] = {"ms": t * 1e3, "GElem_s": n / t / 1e9,
+                          "verdicts": P.verdicts(P.check_props(bad, m4, 0, n, 0, n))[:4]}
+    del bad, perm
+    srt = torch.from_numpy(W.sorted_keys(n, W.PROPS_SORTED_SEED)).to(dev)
+    t = timed(lambda: P.check_props(srt, P.MONO), steps, 1, torch)
+    out["sorted_mono"] = {"ms": t * 1e3, "GElem_s": n / t / 1e9, "alg_GBps": 8 * n / t / 1e9,
+                          "verdicts": P.verdicts(P.check_props(srt, P.MONO))[1:2]}
+    return out
 
 
 def cpu_baseline(W, np):

@@ -131,22 +131,40 @@ __device__ __forceinline__ void insert_value(const PropsArgs &a, int64_t v, bool
     }
 }
 
+// Monotonic comparison with the operator decoded once: LE a<=b, LT a<b,
+// GE b<=a, GT b<a.
+struct MonoCmp {
+    bool swap, strict;
+    __device__ __forceinline__ bool ok(int64_t a, int64_t b) const {
+        const int64_t l = swap ? b : a, r = swap ? a : b;
+        return strict ? l < r : l <= r;
+    }
+};
+
 // Pass 1: Range, Monotonic, the Img part of Bij, the in-Rcd count and the
-// bitmap insertions of Inj / Bij, for every element.
-template <int UNROLL>
+// bitmap insertions of Inj / Bij, for every element.  Each thread takes
+// 16-byte groups (2 int64 or 4 int32); a group's left neighbour for the
+// monotonic check comes from the previous lane (consecutive lanes hold
+// consecutive groups), lane 0 loads it.
+template <bool X64, int UNROLL>
 __global__ __launch_bounds__(kPropsBlock) void props_pass1_kernel(PropsArgs a) {
+    constexpr int kPer = X64 ? 2 : 4;
     const bool want_range = a.mask & IXP_RANGE;
     const bool want_mono = a.mask & IXP_MONO;
     const bool want_set = a.mask & (IXP_INJ | IXP_BIJ);
     const bool want_img = a.mask & IXP_BIJ;
+    const MonoCmp cmp{a.mono_op == IXP_MONO_GE || a.mono_op == IXP_MONO_GT,
+                      a.mono_op == IXP_MONO_LT || a.mono_op == IXP_MONO_GT};
+    const int lane = threadIdx.x & 63;
     unsigned long long c_range = kNone, c_mono = kNone, c_img = kNone, cnt = 0;
     bool dup_seen = false;
-    const int per = a.x64 ? 2 : 4;   // elements per 16-byte group
-    const int64_t groups = a.n / per;
+    const int64_t groups = a.n / kPer;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
     const int64_t g0 = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     typedef uint32_t v4 __attribute__((ext_vector_type(4)));
-    for (int64_t gb = g0; gb < groups; gb += UNROLL * stride) {
+    // every lane of a wave runs the same number of iterations (shuffles below)
+    const int64_t wave_g0 = g0 - lane;
+    for (int64_t gb = g0; wave_g0 + (gb - g0) < groups; gb += UNROLL * stride) {
         v4 raw[UNROLL];
         int64_t gi[UNROLL];
 #pragma unroll
@@ -158,27 +176,31 @@ __global__ __launch_bounds__(kPropsBlock) void props_pass1_kernel(PropsArgs a) {
         }
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) {
-            if (gi[u] >= groups) continue;
-            int64_t val[4];
-            if (a.x64) {
+            int64_t val[kPer];
+            if constexpr (X64) {
                 val[0] = static_cast<int64_t>((static_cast<uint64_t>(raw[u].y) << 32) | raw[u].x);
-                val[1] = static_cast<int64_t>((static_cast<uint64_t>(raw[u].w) << 32) | raw[u].z);
+                val[1 % kPer] = static_cast<int64_t>((static_cast<uint64_t>(raw[u].w) << 32) | raw[u].z);
             } else {
                 val[0] = static_cast<int32_t>(raw[u].x);
-                val[1] = static_cast<int32_t>(raw[u].y);
-                val[2] = static_cast<int32_t>(raw[u].z);
-                val[3] = static_cast<int32_t>(raw[u].w);
+                val[1 % kPer] = static_cast<int32_t>(raw[u].y);
+                val[2 % kPer] = static_cast<int32_t>(raw[u].z);
+                val[3 % kPer] = static_cast<int32_t>(raw[u].w);
             }
-            const int64_t p0 = gi[u] * per;
+            const bool live = gi[u] < groups;
+            const int64_t p0 = gi[u] * kPer;
             int64_t prev = 0;
-            if (want_mono && p0 > 0) prev = load_x(a.x, a.x64, p0 - 1);
-            for (int q = 0; q < per; ++q) {
+            if (want_mono) {
+                prev = __shfl_up(val[kPer - 1], 1, 64);
+                if (lane == 0 && live && p0 > 0) prev = load_x(a.x, X64 ? 1 : 0, p0 - 1);
+            }
+            if (!live) continue;
+#pragma unroll
+            for (int q = 0; q < kPer; ++q) {
                 const int64_t i = p0 + q;
                 const int64_t v = val[q];
                 if (want_range && !(a.lo <= v && v < a.hi) && static_cast<unsigned long long>(i) < c_range)
                     c_range = i;
-                if (want_mono && i > 0 && !mono_ok(prev, v, a.mono_op) &&
-                    static_cast<unsigned long long>(i) < c_mono)
+                if (want_mono && i > 0 && !cmp.ok(prev, v) && static_cast<unsigned long long>(i) < c_mono)
                     c_mono = i;
                 prev = v;
                 if (want_set && a.lo <= v && v < a.hi) {
@@ -190,13 +212,13 @@ __global__ __launch_bounds__(kPropsBlock) void props_pass1_kernel(PropsArgs a) {
             }
         }
     }
-    // the last n % per elements: thread 0 of block 0
+    // the last n % kPer elements: thread 0 of block 0
     if (g0 == 0) {
-        for (int64_t i = groups * per; i < a.n; ++i) {
-            const int64_t v = load_x(a.x, a.x64, i);
+        for (int64_t i = groups * kPer; i < a.n; ++i) {
+            const int64_t v = load_x(a.x, X64 ? 1 : 0, i);
             if (want_range && !(a.lo <= v && v < a.hi) && static_cast<unsigned long long>(i) < c_range)
                 c_range = i;
-            if (want_mono && i > 0 && !mono_ok(load_x(a.x, a.x64, i - 1), v, a.mono_op) &&
+            if (want_mono && i > 0 && !cmp.ok(load_x(a.x, X64 ? 1 : 0, i - 1), v) &&
                 static_cast<unsigned long long>(i) < c_mono)
                 c_mono = i;
             if (want_set && a.lo <= v && v < a.hi) {
@@ -212,7 +234,7 @@ __global__ __launch_bounds__(kPropsBlock) void props_pass1_kernel(PropsArgs a) {
     c_img = wave_min_u64(c_img);
     cnt = wave_sum_u64(cnt);
     const bool any_dup = ballot(dup_seen) != 0;
-    if ((threadIdx.x & 63) == 0) {
+    if (lane == 0) {
         if (c_range != kNone) atomicMin(&a.st->fv_range, c_range);
         if (c_mono != kNone) atomicMin(&a.st->fv_mono, c_mono);
         if (c_img != kNone) atomicMin(&a.st->fv_img, c_img);
@@ -640,7 +662,10 @@ extern "C" int ixp_check_props(const void *x, int32_t x_t, int64_t n, uint32_t m
     if (main_mask && n > 0) {
         PropsArgs b = a;
         b.mask = main_mask;
-        IXP_LAUNCH("props_pass1", props_pass1_kernel<4>, dim3(grid), dim3(kPropsBlock), 0, st, b);
+        if (b.x64)
+            IXP_LAUNCH("props_pass1", (props_pass1_kernel<true, 4>), dim3(grid), dim3(kPropsBlock), 0, st, b);
+        else
+            IXP_LAUNCH("props_pass1", (props_pass1_kernel<false, 4>), dim3(grid), dim3(kPropsBlock), 0, st, b);
         if (main_mask & (IXP_INJ | IXP_BIJ)) {
             IXP_LAUNCH("props_first", props_first_kernel, dim3(grid), dim3(kPropsBlock), 0, st, b);
             IXP_LAUNCH("props_second", props_second_kernel, dim3(grid), dim3(kPropsBlock), 0, st, b,

@@ -16,8 +16,8 @@
 //   [A_k + j*TILE, A_k + (j+1)*TILE) ∩ [o_k, o_k + s_k),   A_k = o_k rounded down to 4.
 // Kernels (all stream-ordered, capturable in one HIP graph):
 //   seg_setup -- one workgroup: validates the shape, scans it into row offsets
-//                and item offsets, writes one descriptor per item, resets the
-//                work queue;
+//                and item offsets, resets the work queue;
+//   seg_items -- one thread per row writes the row's item descriptors;
 //   seg_count -- one wave per item counts the trues of the items whose row
 //                spans several items (partition) or of every item (filter);
 //   seg_scan  -- per row (partition) / over all items (filter): turns item
@@ -118,7 +118,8 @@ __global__ __launch_bounds__(kSetupThreads) void seg_setup_kernel(SegArgs a) {
             const int64_t k = r0 + j;
             s[j] = k < a.m ? a.shape[k] : 0;
             if (s[j] < 0) atomicOr(&bad, 1);
-            sum_s += s[j] < 0 ? 0 : s[j];
+            s[j] = s[j] < 0 ? 0 : s[j];
+            sum_s += s[j];
         }
         int64_t tot_s;
         const int64_t off0 = carry_off + block_exclusive_scan_1024(sum_s, lds_a, &tot_s);
@@ -129,11 +130,10 @@ __global__ __launch_bounds__(kSetupThreads) void seg_setup_kernel(SegArgs a) {
             int64_t o = off0;
 #pragma unroll
             for (int j = 0; j < kSetupPer; ++j) {
-                const int64_t sk = s[j] < 0 ? 0 : s[j];
                 const int64_t ak = o & ~int64_t{3};
-                nitems[j] = sk > 0 ? ceil_div(o + sk - ak, a.tile) : 0;
+                nitems[j] = s[j] > 0 ? ceil_div(o + s[j] - ak, a.tile) : 0;
                 sum_it += nitems[j];
-                o += sk;
+                o += s[j];
             }
         }
         int64_t tot_it;
@@ -145,25 +145,8 @@ __global__ __launch_bounds__(kSetupThreads) void seg_setup_kernel(SegArgs a) {
             if (k < a.m) {
                 a.offsets[k] = o;
                 a.item_off[k] = it;
-                const int64_t sk = s[j] < 0 ? 0 : s[j];
-                const int64_t ak = o & ~int64_t{3};
-                for (int64_t q = 0; q < nitems[j]; ++q) {
-                    const int64_t idx = it + q;
-                    if (idx < a.max_items) {
-                        SegItem d;
-                        d.base = ak + q * a.tile;
-                        d.lo = d.base > o ? d.base : o;
-                        d.hi = d.base + a.tile < o + sk ? d.base + a.tile : o + sk;
-                        d.tbase = 0;
-                        d.fbase = 0;
-                        d.row = static_cast<int32_t>(k);
-                        d.kind = (nitems[j] == 1 ? 1 : 0) | (q == 0 ? 2 : 0);
-                        d.count = 0;
-                        a.items[idx] = d;
-                    }
-                }
             }
-            o += s[j] < 0 ? 0 : s[j];
+            o += s[j];
             it += nitems[j];
         }
         carry_off += tot_s;
@@ -177,6 +160,28 @@ __global__ __launch_bounds__(kSetupThreads) void seg_setup_kernel(SegArgs a) {
         *a.num_items = ok ? carry_items : 0;
         *a.ticket = 0;
         *a.err = ok ? 0 : kErrShape;
+    }
+}
+
+// One thread per row writes the row's item descriptors.
+__global__ __launch_bounds__(256) void seg_items_kernel(SegArgs a) {
+    const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= a.m || *a.num_items == 0) return;
+    const int64_t o = a.offsets[k], e = a.offsets[k + 1];
+    const int64_t i0 = a.item_off[k], i1 = a.item_off[k + 1];
+    const int64_t ak = o & ~int64_t{3};
+    for (int64_t idx = i0; idx < i1; ++idx) {
+        const int64_t q = idx - i0;
+        SegItem d;
+        d.base = ak + q * a.tile;
+        d.lo = d.base > o ? d.base : o;
+        d.hi = d.base + a.tile < e ? d.base + a.tile : e;
+        d.tbase = 0;
+        d.fbase = 0;
+        d.row = static_cast<int32_t>(k);
+        d.kind = (i1 - i0 == 1 ? 1 : 0) | (q == 0 ? 2 : 0);
+        d.count = 0;
+        a.items[idx] = d;
     }
 }
 
@@ -417,10 +422,12 @@ template <class Pred>
 int launch_all(const SegArgs &a, const Pred &p, const SegGeom &g, int mode, int idx_t, hipStream_t st) {
     IXP_LAUNCH("seg_setup", seg_setup_kernel, dim3(1), dim3(kSetupThreads), 0, st, a);
     if (launch_status() != IXP_OK) return IXP_EHIP;
+    const uint32_t rblocks = static_cast<uint32_t>(ceil_div(a.m > 0 ? a.m : 1, 256));
+    IXP_LAUNCH("seg_items", seg_items_kernel, dim3(rblocks), dim3(256), 0, st, a);
+    if (launch_status() != IXP_OK) return IXP_EHIP;
     const int cus = device_cus();
     IXP_LAUNCH("seg_count", (seg_count_kernel<Pred>), dim3(cus * 8), dim3(256), 0, st, a, p);
     if (launch_status() != IXP_OK) return IXP_EHIP;
-    const uint32_t rblocks = static_cast<uint32_t>(ceil_div(a.m > 0 ? a.m : 1, 256));
     if (mode == IXP_MODE_PARTITION) {
         IXP_LAUNCH("seg_scan_rows", seg_scan_rows_kernel, dim3(rblocks), dim3(256), 0, st, a);
     } else {

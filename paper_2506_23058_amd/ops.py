@@ -380,3 +380,43 @@ class PartitionScatter(torch.autograd.Function):
 
 def partition_scatter(keys, payload, pred, mode=L.MODE_PARTITION):
     return PartitionScatter.apply(keys, payload, pred, mode)
+
+
+def _tune_cache_path():
+    import os
+    return os.environ.get("IXP_TUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "ixpart", "tune.json"))
+
+
+def autotuned_tiling(keys, shape, pred, mode=L.MODE_PARTITION, idx_dtype=torch.int32,
+                     want_flags=True, reps: int = 5):
+    """Tiling for a segmented call from the autotuner cache (a JSON file keyed
+    by GPU architecture, key dtype, mode, index dtype and the power-of-two bins
+    of n and m; path in $IXP_TUNE_CACHE), running the tuner on a miss."""
+    import json
+    import math
+    import os
+    arch = torch.cuda.get_device_properties(keys.device).gcnArchName.split(":")[0]
+    n, m = keys.numel(), shape.numel()
+    key = "|".join([arch, str(keys.dtype), str(mode), str(idx_dtype), pred.kind.__str__(),
+                    f"n2^{int(math.log2(max(n, 1)))}", f"m2^{int(math.log2(max(m, 1)))}"])
+    path = _tune_cache_path()
+    cache = {}
+    if os.path.exists(path):
+        try:
+            with open(path) as f:
+                cache = json.load(f)
+        except (OSError, ValueError):
+            cache = {}
+    if key in cache:
+        return tuple(cache[key]["tiling"]), cache[key]["ms"], True
+    tiling, ms = tune_segmented(keys, shape, pred, mode, idx_dtype, want_flags, reps)
+    cache[key] = {"tiling": list(tiling), "ms": ms}
+    try:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        with open(path + ".tmp", "w") as f:
+            json.dump(cache, f, indent=1, sort_keys=True)
+        os.replace(path + ".tmp", path)
+    except OSError:
+        pass
+    return tiling, ms, False
