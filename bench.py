@@ -79,6 +79,8 @@ def main():
                     help="headline steps only (for profiler runs)")
     ap.add_argument("--with-copy", action="store_true",
                     help="also run one plain device copy of the input (counter calibration)")
+    ap.add_argument("--section", default=None,
+                    help="run only this section (segmented, autograd, props, flat_extra) and print it")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -93,6 +95,11 @@ def main():
     import workloads as W
 
     dev = torch.device("cuda:0")
+    if args.section:
+        fn = {"segmented": section_segmented, "autograd": section_autograd,
+              "props": section_props}[args.section]
+        print(json.dumps({args.section: fn(args, torch, np, P, W, dev)}))
+        return
     n = W.FLAT_LARGE_N
     sels = W.FLAT_LARGE_SELECTIVITIES
     x = torch.from_numpy(W.f32_uniform(n, W.FLAT_LARGE_SEED)).to(dev)

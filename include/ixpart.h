@@ -107,10 +107,11 @@ int ixp_partition(const void *keys, int32_t key_t, int64_t n,
 
 /* ---- segmented partition (partition2L / filter_seg) ----------------------- */
 
-/* Tile shape of the segmented kernels: `block` threads (256 or 512) each
- * holding `rows` x 4 consecutive-by-quads elements (rows in {2,4,8}); a tile
- * is block*rows*4 elements.  `wgs_per_cu` sizes the persistent grid (0 = 4).
- * A NULL tuning pointer selects the library default. */
+/* Tile shape of the segmented kernels: `block` threads (256, 512 or 1024)
+ * each holding `rows` x 4 elements (rows in {2,4,8}, tile <= 16384); a tile
+ * is block*rows*4 elements.  `wgs_per_cu` (1..64, 0 = as many as fit) sizes
+ * the grid of the main kernel, whose workgroups pull work items from an atomic
+ * queue until it is empty.  A NULL tuning pointer selects the default. */
 typedef struct {
     int32_t block;
     int32_t rows;
@@ -221,7 +222,9 @@ enum { IXP_MONO_LE = 0, IXP_MONO_LT = 1, IXP_MONO_GE = 2, IXP_MONO_GT = 3 };
  *          only); 8 Z not strictly increasing inside a class (FILTER: among
  *          kept elements); 16 Y[Z[i]] != X[i] bitwise.  first_violation = the
  *          least index failing one of 2..16, n if only 1 fails.
- * Intervals are half-open; Rcd [lo,hi) must span at most 2^40 values. */
+ * Intervals are half-open.  Inj and Bij need a workspace of about 4.25 bytes
+ * per value of Rcd [lo,hi) (two bitmaps and a first-index table), plus 8
+ * bytes per element when n >= 2^16; Rcd may span at most 2^36 values. */
 typedef struct {
     int32_t holds;
     int32_t reserved;

@@ -319,13 +319,15 @@ struct Tile {
                 }
             }
         }
+        // validity from 32-bit offsets relative to lo (a tile spans < 2^31)
+        const int32_t l0 = static_cast<int32_t>(base - lo) + wave * kPerWave + lane * VEC;
+        const uint32_t span = static_cast<uint32_t>(hi - lo);
 #pragma unroll
         for (int r = 0; r < ROWS; ++r) {
-            const int64_t p0 = pos(base, wave, r, lane, 0);
 #pragma unroll
             for (int q = 0; q < VEC; ++q) {
-                const int64_t p = p0 + q;
-                const bool valid = p >= lo && p < hi;
+                const int32_t l = l0 + r * (kWave * VEC) + q;
+                const bool valid = static_cast<uint32_t>(l) < span;
                 key[r][q] = kv[r][q];
                 const bool f = valid && pred(kv[r][q], fv[r][q]);
                 vbits |= static_cast<uint64_t>(valid) << (r * VEC + q);
@@ -333,6 +335,12 @@ struct Tile {
             }
         }
         (void)n;
+    }
+
+    // True when this wave's run of the tile meets [lo, hi) (wave-uniform).
+    __device__ static __forceinline__ bool wave_live(int64_t base, int64_t lo, int64_t hi, int wave) {
+        const int64_t w0 = base + static_cast<int64_t>(wave) * kPerWave;
+        return w0 < hi && w0 + kPerWave > lo;
     }
 
     __device__ __forceinline__ bool flag(int r, int q) const { return (fbits >> (r * VEC + q)) & 1ull; }

@@ -207,6 +207,7 @@ __global__ __launch_bounds__((FlatCfg<MODE, VEC>::kBlock)) void flat_scan_kernel
 
     Idx *out_idx = static_cast<Idx *>(a.out_idx);
     const bool full = hi - lo == kTile;   // wave-uniform
+    const int32_t l0 = wave * T::kPerWave + lane * VEC;
 #pragma unroll
     for (int r = 0; r < kRows; ++r) {
         const int64_t p0 = T::pos(lo, wave, r, lane, 0);
@@ -215,7 +216,7 @@ __global__ __launch_bounds__((FlatCfg<MODE, VEC>::kBlock)) void flat_scan_kernel
 #pragma unroll
         for (int q = 0; q < VEC; ++q) {
             const uint32_t rt = tile.rank[r][q];
-            const uint32_t rf = static_cast<uint32_t>(p0 + q - lo) - rt;
+            const uint32_t rf = static_cast<uint32_t>(l0 + r * (kWave * VEC) + q) - rt;
             const bool f = tile.flag(r, q);
             const bool ok = tile.valid(r, q);
             vm |= static_cast<uint32_t>(ok) << q;

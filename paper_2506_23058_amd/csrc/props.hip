@@ -56,6 +56,14 @@ struct PropsArgs {
     uint32_t *first;      // least index of each repeated value (n < 2^32) or...
     unsigned long long *first64;   // ... 64-bit when n >= 2^32
     int64_t width;        // hi - lo when a bitmap is in use
+    // Bucketed Inj/Bij (see props_place_kernel): values of Rcd grouped in
+    // buckets of 2^kBucketShift consecutive values.
+    int32_t bucketed;
+    int32_t nbuckets;
+    unsigned long long *bucket_total;   // [nbuckets]
+    unsigned long long *bucket_start;   // [nbuckets]
+    unsigned long long *wg_base;        // [gridDim of pass 1][nbuckets]
+    unsigned long long *records;        // [entries inside Rcd]
     // FiltPart
     const uint32_t *fp_src;
     const uint32_t *fp_dst;
@@ -93,8 +101,10 @@ __device__ __forceinline__ bool mono_ok(int64_t a, int64_t b, int op) {
     }
 }
 
-__global__ void props_init_kernel(PropsState *st, uint32_t *seen, uint32_t *dup, int64_t words) {
+__global__ void props_init_kernel(PropsState *st, uint32_t *seen, uint32_t *dup, int64_t words,
+                                  unsigned long long *zero2, int64_t nzero2) {
     const int64_t i0 = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    for (int64_t i = i0; i < nzero2; i += static_cast<int64_t>(gridDim.x) * blockDim.x) zero2[i] = 0;
     if (i0 == 0 && st) {
         st->fv_range = st->fv_mono = st->fv_img = st->fv_inj = kNone;
         st->in_count = 0;
@@ -146,9 +156,23 @@ struct MonoCmp {
 // 16-byte groups (2 int64 or 4 int32); a group's left neighbour for the
 // monotonic check comes from the previous lane (consecutive lanes hold
 // consecutive groups), lane 0 loads it.
+constexpr int kBucketShift = 20;              // 2^20 values: a 128 KiB LDS bitmap
+constexpr int kMaxBuckets = 4096;
+
+__device__ __forceinline__ void note_value(const PropsArgs &a, int64_t v, bool *dup_seen,
+                                           uint32_t *hist) {
+    if (a.bucketed) atomicAdd(hist + ((v - a.lo) >> kBucketShift), 1u);
+    else insert_value(a, v, dup_seen);
+}
+
 template <bool X64, int UNROLL>
 __global__ __launch_bounds__(kPropsBlock) void props_pass1_kernel(PropsArgs a) {
     constexpr int kPer = X64 ? 2 : 4;
+    extern __shared__ uint32_t hist[];   // nbuckets counters when bucketed
+    if (a.bucketed) {
+        for (int b = threadIdx.x; b < a.nbuckets; b += blockDim.x) hist[b] = 0;
+        __syncthreads();
+    }
     const bool want_range = a.mask & IXP_RANGE;
     const bool want_mono = a.mask & IXP_MONO;
     const bool want_set = a.mask & (IXP_INJ | IXP_BIJ);
@@ -207,7 +231,7 @@ __global__ __launch_bounds__(kPropsBlock) void props_pass1_kernel(PropsArgs a) {
                     ++cnt;
                     if (want_img && !(a.ilo <= v && v < a.ihi) && static_cast<unsigned long long>(i) < c_img)
                         c_img = i;
-                    insert_value(a, v, &dup_seen);
+                    note_value(a, v, &dup_seen, hist);
                 }
             }
         }
@@ -225,8 +249,17 @@ __global__ __launch_bounds__(kPropsBlock) void props_pass1_kernel(PropsArgs a) {
                 ++cnt;
                 if (want_img && !(a.ilo <= v && v < a.ihi) && static_cast<unsigned long long>(i) < c_img)
                     c_img = i;
-                insert_value(a, v, &dup_seen);
+                note_value(a, v, &dup_seen, hist);
             }
+        }
+    }
+    if (a.bucketed) {
+        // reserve this workgroup's range inside every bucket it fills
+        __syncthreads();
+        for (int b = threadIdx.x; b < a.nbuckets; b += blockDim.x) {
+            const uint32_t c = hist[b];
+            a.wg_base[static_cast<int64_t>(blockIdx.x) * a.nbuckets + b] =
+                c ? atomicAdd(a.bucket_total + b, static_cast<unsigned long long>(c)) : 0ull;
         }
     }
     c_range = wave_min_u64(c_range);
@@ -241,6 +274,212 @@ __global__ __launch_bounds__(kPropsBlock) void props_pass1_kernel(PropsArgs a) {
         if (cnt) atomicAdd(&a.st->in_count, cnt);
         if (any_dup) atomicOr(&a.st->dup_found, 1u);
     }
+}
+
+// Bucketed Inj/Bij.  Random device-scope atomics on a bitmap in HBM run far
+// below the memory bandwidth, so the values inside Rcd are first grouped by
+// bucket (2^20 consecutive values each): pass 1 counts them per workgroup and
+// reserves each workgroup's range in each bucket; props_place writes one
+// 8-byte record (index << 20 | offset in bucket) per value into its bucket;
+// props_check gives each bucket one workgroup, whose 128 KiB LDS bitmap
+// finds the repeated values with LDS atomics and, for Bij, the least value of
+// Img left unset.  Repeats are then located exactly by props_first/second.
+__global__ __launch_bounds__(1024) void props_bucket_scan_kernel(PropsArgs a) {
+    __shared__ unsigned long long lds[16];
+    constexpr int kPer = kMaxBuckets / 1024;
+    const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
+    unsigned long long v[kPer], run = 0;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int b = tid * kPer + k;
+        v[k] = b < a.nbuckets ? a.bucket_total[b] : 0ull;
+        run += v[k];
+    }
+    unsigned long long inc = run;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const unsigned long long o = __shfl_up(inc, off, 64);
+        if (lane >= off) inc += o;
+    }
+    if (lane == 63) lds[wave] = inc;
+    __syncthreads();
+    unsigned long long before = 0;
+    for (int w = 0; w < wave; ++w) before += lds[w];
+    unsigned long long acc = before + inc - run;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int b = tid * kPer + k;
+        if (b < a.nbuckets) a.bucket_start[b] = acc;
+        acc += v[k];
+    }
+}
+
+// Placement works in rounds of UNROLL groups per thread (the same elements
+// per workgroup as pass 1).  A round's records are first grouped by bucket in
+// LDS (a local counting sort: LDS atomics give ranks, a scan of the round's
+// bucket counts gives offsets), then written bucket run by bucket run, so
+// global stores form contiguous runs instead of scattered 8-byte writes.
+template <bool X64, int UNROLL>
+__global__ __launch_bounds__(kPropsBlock) void props_place_kernel(PropsArgs a) {
+    constexpr int kPer = X64 ? 2 : 4;
+    constexpr int kRound = kPropsBlock * UNROLL * kPer;   // records per round at most
+    extern __shared__ unsigned long long base[];          // [nb] global write position
+    const int nb = a.nbuckets;
+    uint32_t *rhist = reinterpret_cast<uint32_t *>(base + nb);   // [nb] round counts
+    uint32_t *roff = rhist + nb;                                 // [nb] round offsets
+    unsigned long long *stage = reinterpret_cast<unsigned long long *>(roff + nb);   // 8-aligned: 16 nb bytes in
+    uint16_t *sbkt = reinterpret_cast<uint16_t *>(stage + kRound);
+    __shared__ uint32_t wsum[kPropsBlock / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
+    for (int b = tid; b < nb; b += kPropsBlock) {
+        base[b] = a.bucket_start[b] + a.wg_base[static_cast<int64_t>(blockIdx.x) * nb + b];
+        rhist[b] = 0;
+    }
+    __syncthreads();
+    const int64_t groups = a.n / kPer;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    const int64_t g0 = static_cast<int64_t>(blockIdx.x) * blockDim.x + tid;
+    const int64_t wg_g0 = static_cast<int64_t>(blockIdx.x) * blockDim.x;   // workgroup-uniform
+    typedef uint32_t v4 __attribute__((ext_vector_type(4)));
+    for (int64_t rb = 0; wg_g0 + rb < groups; rb += UNROLL * stride) {
+        unsigned long long rec[UNROLL * kPer];
+        int bk[UNROLL * kPer];
+        uint32_t rk[UNROLL * kPer];
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+            const int64_t gi = g0 + rb + u * stride;
+            v4 raw = gi < groups ? __builtin_nontemporal_load(reinterpret_cast<const v4 *>(a.x) + gi)
+                                 : v4{0, 0, 0, 0};
+            int64_t val[kPer];
+            if constexpr (X64) {
+                val[0] = static_cast<int64_t>((static_cast<uint64_t>(raw.y) << 32) | raw.x);
+                val[1 % kPer] = static_cast<int64_t>((static_cast<uint64_t>(raw.w) << 32) | raw.z);
+            } else {
+                val[0] = static_cast<int32_t>(raw.x);
+                val[1 % kPer] = static_cast<int32_t>(raw.y);
+                val[2 % kPer] = static_cast<int32_t>(raw.z);
+                val[3 % kPer] = static_cast<int32_t>(raw.w);
+            }
+#pragma unroll
+            for (int q = 0; q < kPer; ++q) {
+                const int k = u * kPer + q;
+                const int64_t v = val[q];
+                const bool in = gi < groups && a.lo <= v && v < a.hi;
+                const uint64_t o = static_cast<uint64_t>(v - a.lo);
+                bk[k] = in ? static_cast<int>(o >> kBucketShift) : -1;
+                rec[k] = (static_cast<unsigned long long>(gi * kPer + q) << kBucketShift) |
+                         (o & ((1ull << kBucketShift) - 1));
+                rk[k] = in ? atomicAdd(rhist + bk[k], 1u) : 0u;
+            }
+        }
+        __syncthreads();
+        // exclusive scan of the round's bucket counts (threads own buckets
+        // b = tid, tid + 256, ...; a sequential pass per thread suffices for
+        // nb <= 4096 after a block scan of the per-thread sums)
+        uint32_t mysum = 0;
+        for (int b = tid; b < nb; b += kPropsBlock) mysum += rhist[b];
+        uint32_t inc = mysum;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t o = __shfl_up(inc, off, 64);
+            if (lane >= off) inc += o;
+        }
+        if (lane == 63) wsum[wave] = inc;
+        __syncthreads();
+        uint32_t before = inc - mysum;
+        for (int w = 0; w < wave; ++w) before += wsum[w];
+        // thread tid lays out its buckets tid, tid + 256, ... after its
+        // exclusive prefix; any bucket order inside a round works, since the
+        // write pass reads each slot's bucket back
+        for (int b = tid; b < nb; b += kPropsBlock) {
+            roff[b] = before;
+            before += rhist[b];
+        }
+        __syncthreads();
+        uint32_t round_total = 0;
+        for (int w = 0; w < kPropsBlock / 64; ++w) round_total += wsum[w];
+#pragma unroll
+        for (int k = 0; k < UNROLL * kPer; ++k) {
+            if (bk[k] >= 0) {
+                const uint32_t slot = roff[bk[k]] + rk[k];
+                stage[slot] = rec[k];
+                sbkt[slot] = static_cast<uint16_t>(bk[k]);
+            }
+        }
+        __syncthreads();
+        for (uint32_t sl = tid; sl < round_total; sl += kPropsBlock) {
+            const int b = sbkt[sl];
+            __builtin_nontemporal_store(stage[sl], a.records + base[b] + (sl - roff[b]));
+        }
+        __syncthreads();
+        for (int b = tid; b < nb; b += kPropsBlock) {
+            base[b] += rhist[b];
+            rhist[b] = 0;
+        }
+        __syncthreads();
+    }
+    // the last n % kPer elements: thread 0 of block 0, directly
+    if (g0 == 0) {
+        for (int64_t i = groups * kPer; i < a.n; ++i) {
+            const int64_t v = load_x(a.x, X64 ? 1 : 0, i);
+            if (!(a.lo <= v && v < a.hi)) continue;
+            const uint64_t o = static_cast<uint64_t>(v - a.lo);
+            const int b = static_cast<int>(o >> kBucketShift);
+            const unsigned long long rec = (static_cast<unsigned long long>(i) << kBucketShift) |
+                                           (o & ((1ull << kBucketShift) - 1));
+            a.records[base[b]] = rec;
+            base[b] += 1;
+        }
+    }
+}
+
+constexpr int kCheckThreads = 1024;
+constexpr int kBucketWords = (1 << kBucketShift) / 32;
+
+__global__ __launch_bounds__(kCheckThreads) void props_check_kernel(PropsArgs a) {
+    __shared__ uint32_t bits[kBucketWords];
+    const int b = blockIdx.x;
+    const int tid = threadIdx.x;
+    for (int w = tid; w < kBucketWords; w += kCheckThreads) bits[w] = 0;
+    __syncthreads();
+    const unsigned long long r0 = a.bucket_start[b], r1 = r0 + a.bucket_total[b];
+    bool dup_seen = false;
+    for (unsigned long long r = r0 + tid; r < r1; r += kCheckThreads) {
+        const unsigned long long rec = __builtin_nontemporal_load(a.records + r);
+        const uint32_t off = static_cast<uint32_t>(rec & ((1ull << kBucketShift) - 1));
+        const uint32_t bit = 1u << (off & 31);
+        const uint32_t old = atomicOr(bits + (off >> 5), bit);
+        if (old & bit) {
+            const uint64_t o = (static_cast<uint64_t>(b) << kBucketShift) + off;   // value - lo
+            atomicOr(a.dup + (o >> 5), 1u << (o & 31));
+            if (a.first64) a.first64[o] = ~0ull;
+            else a.first[o] = ~0u;
+            dup_seen = true;
+        }
+    }
+    const bool any_dup = ballot(dup_seen) != 0;
+    if ((tid & 63) == 0 && any_dup) atomicOr(&a.st->dup_found, 1u);
+    if (!(a.mask & IXP_BIJ)) return;
+    __syncthreads();
+    // least value of Img inside this bucket whose bit is clear
+    const int64_t v0 = a.lo + (static_cast<int64_t>(b) << kBucketShift);
+    const int64_t lo_b = a.ilo > v0 ? a.ilo - v0 : 0;
+    const int64_t hi_b = a.ihi - v0 < (int64_t{1} << kBucketShift) ? a.ihi - v0 : (int64_t{1} << kBucketShift);
+    unsigned long long c = kNone;
+    if (lo_b < hi_b) {
+        for (int64_t w = (lo_b >> 5) + tid; w <= ((hi_b - 1) >> 5); w += kCheckThreads) {
+            uint32_t clear = ~bits[w];
+            const int64_t wb = w << 5;
+            if (wb < lo_b) clear &= ~0u << (lo_b - wb);
+            if (wb + 32 > hi_b) clear &= (hi_b - wb) >= 32 ? ~0u : ((1u << (hi_b - wb)) - 1u);
+            if (clear) {
+                const unsigned long long v = static_cast<unsigned long long>(v0 + wb + __builtin_ctz(clear));
+                if (v < c) c = v;
+            }
+        }
+    }
+    c = wave_min_u64(c);
+    if ((tid & 63) == 0 && c != kNone) atomicMin(&a.st->missing, c);
 }
 
 // Value inserted by the Inj / Bij bitmap for element i, or false.
@@ -287,6 +526,7 @@ __global__ __launch_bounds__(kPropsBlock) void props_second_kernel(PropsArgs a, 
 
 // Bij failing only on the count: least value of Img whose bit is clear.
 __global__ __launch_bounds__(kPropsBlock) void props_missing_kernel(PropsArgs a) {
+    if (a.bucketed) return;
     PropsState *st = a.st;
     const unsigned long long inj = st->fv_inj, img = st->fv_img;
     if (inj != kNone || img != kNone) return;
@@ -566,6 +806,25 @@ int launch_filtpart(PropsArgs a, const Pred &pred, hipStream_t st, int grid) {
 using namespace ixp;
 
 namespace {
+constexpr int kPass1Grid = 2048;   // fixed, so the workspace size does not depend on the device
+
+// Inj/Bij take the bucketed path when Rcd spans at most kMaxBuckets buckets
+// and the array is large enough for the extra passes to pay.
+int buckets_for(int64_t n, uint32_t mask, const ixp_prop_args *a) {
+    if (!(mask & (IXP_INJ | IXP_BIJ)) || !a) return 0;
+    const int64_t w = a->hi - a->lo;
+    if (w <= 0 || n < (int64_t{1} << 16) || n >= (int64_t{1} << 43)) return 0;
+    const int64_t b = (w + (int64_t{1} << kBucketShift) - 1) >> kBucketShift;
+    return b <= kMaxBuckets ? static_cast<int>(b) : 0;
+}
+
+size_t bucket_bytes(int64_t n, int nb) {
+    if (!nb) return 0;
+    return round_up(static_cast<size_t>(nb) * 8, 256) * 2 +
+           round_up(static_cast<size_t>(kPass1Grid) * nb * 8, 256) +
+           round_up(static_cast<size_t>(n) * 8, 256);
+}
+
 int64_t rcd_width(int64_t n, uint32_t mask, const ixp_prop_args *a) {
     int64_t w = 0;
     if ((mask & (IXP_INJ | IXP_BIJ)) && a) w = a->hi - a->lo;
@@ -583,7 +842,7 @@ extern "C" size_t ixp_check_props_workspace(int64_t n, uint32_t mask, const ixp_
     const size_t first_bytes = static_cast<size_t>(w) * (n >= (int64_t{1} << 32) ? 8 : 4);
     const int64_t tiles = (mask & IXP_FILTPART) ? ceil_div(n, kFpTile) : 0;
     return kPropsHeader + 2 * round_up(words * 4, 256) + round_up(first_bytes, 256) +
-           round_up(static_cast<size_t>(tiles) * 16, 256);
+           round_up(static_cast<size_t>(tiles) * 16, 256) + bucket_bytes(n, buckets_for(n, mask, a));
 }
 
 extern "C" int ixp_check_props(const void *x, int32_t x_t, int64_t n, uint32_t mask,
@@ -646,26 +905,49 @@ extern "C" int ixp_check_props(const void *x, int32_t x_t, int64_t n, uint32_t m
     const size_t first_bytes = static_cast<size_t>(w) * (n >= (int64_t{1} << 32) ? 8 : 4);
     a.fp_tmax = reinterpret_cast<int64_t *>(fp + round_up(first_bytes, 256));
     a.fp_tiles = (mask & IXP_FILTPART) ? ceil_div(n, kFpTile) : 0;
+    a.nbuckets = buckets_for(n, mask, pa);
+    a.bucketed = a.nbuckets > 0 ? 1 : 0;
+    if (a.bucketed) {
+        char *bp = reinterpret_cast<char *>(a.fp_tmax) + round_up(static_cast<size_t>(a.fp_tiles) * 16, 256);
+        const size_t bb = round_up(static_cast<size_t>(a.nbuckets) * 8, 256);
+        a.bucket_total = reinterpret_cast<unsigned long long *>(bp);
+        a.bucket_start = reinterpret_cast<unsigned long long *>(bp + bb);
+        a.wg_base = reinterpret_cast<unsigned long long *>(bp + 2 * bb);
+        a.records = reinterpret_cast<unsigned long long *>(
+            bp + 2 * bb + round_up(static_cast<size_t>(kPass1Grid) * a.nbuckets * 8, 256));
+    }
     a.fp_src = static_cast<const uint32_t *>(pa->fp_src);
     a.fp_dst = static_cast<const uint32_t *>(pa->fp_dst);
     a.fp_split = pa->fp_split;
     a.fp_mode = pa->fp_mode;
 
-    const int cus = device_cus();
-    const int grid = cus * 8;
+    const int grid = kPass1Grid;
     const int64_t iwords = words > 0 ? words : 1;
     const uint32_t iblocks = static_cast<uint32_t>(ceil_div(iwords / 4 + 1, 256) < 4096 ? ceil_div(iwords / 4 + 1, 256) : 4096);
-    IXP_LAUNCH("props_init", props_init_kernel, dim3(iblocks), dim3(256), 0, st, a.st, a.seen, a.dup, words);
+    IXP_LAUNCH("props_init", props_init_kernel, dim3(iblocks), dim3(256), 0, st, a.st, a.seen, a.dup, words,
+               a.bucket_total, a.bucketed ? static_cast<int64_t>(a.nbuckets) : int64_t{0});
     if (launch_status() != IXP_OK) return IXP_EHIP;
 
     const uint32_t main_mask = mask & (IXP_RANGE | IXP_MONO | IXP_INJ | IXP_BIJ);
     if (main_mask && n > 0) {
         PropsArgs b = a;
         b.mask = main_mask;
+        const size_t hist_lds = b.bucketed ? static_cast<size_t>(b.nbuckets) * 4 : 0;
         if (b.x64)
-            IXP_LAUNCH("props_pass1", (props_pass1_kernel<true, 4>), dim3(grid), dim3(kPropsBlock), 0, st, b);
+            IXP_LAUNCH("props_pass1", (props_pass1_kernel<true, 4>), dim3(grid), dim3(kPropsBlock), hist_lds, st, b);
         else
-            IXP_LAUNCH("props_pass1", (props_pass1_kernel<false, 4>), dim3(grid), dim3(kPropsBlock), 0, st, b);
+            IXP_LAUNCH("props_pass1", (props_pass1_kernel<false, 4>), dim3(grid), dim3(kPropsBlock), hist_lds, st, b);
+        if (b.bucketed) {
+            IXP_LAUNCH("props_bucket_scan", props_bucket_scan_kernel, dim3(1), dim3(1024), 0, st, b);
+            // base[nb] + round counts/offsets [2 nb] (+pad) + staged records and bucket ids
+            const size_t place_lds = static_cast<size_t>(b.nbuckets) * 16 +
+                                     static_cast<size_t>(kPropsBlock * 4 * (b.x64 ? 2 : 4)) * 10;
+            if (b.x64)
+                IXP_LAUNCH("props_place", (props_place_kernel<true, 4>), dim3(grid), dim3(kPropsBlock), place_lds, st, b);
+            else
+                IXP_LAUNCH("props_place", (props_place_kernel<false, 4>), dim3(grid), dim3(kPropsBlock), place_lds, st, b);
+            IXP_LAUNCH("props_check", props_check_kernel, dim3(b.nbuckets), dim3(kCheckThreads), 0, st, b);
+        }
         if (main_mask & (IXP_INJ | IXP_BIJ)) {
             IXP_LAUNCH("props_first", props_first_kernel, dim3(grid), dim3(kPropsBlock), 0, st, b);
             IXP_LAUNCH("props_second", props_second_kernel, dim3(grid), dim3(kPropsBlock), 0, st, b,
@@ -685,7 +967,8 @@ extern "C" int ixp_check_props(const void *x, int32_t x_t, int64_t n, uint32_t m
         f.hi = n;
         if (main_mask & (IXP_INJ | IXP_BIJ)) {
             IXP_LAUNCH("props_init_fp", props_init_kernel, dim3(iblocks), dim3(256), 0, st,
-                       static_cast<PropsState *>(nullptr), a.seen, a.dup, words);
+                       static_cast<PropsState *>(nullptr), a.seen, a.dup, words,
+                       static_cast<unsigned long long *>(nullptr), int64_t{0});
         }
         int rc = IXP_OK;
         switch (hp.kind) {

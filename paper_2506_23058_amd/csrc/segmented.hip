@@ -63,6 +63,7 @@ struct SegArgs {
     int32_t *err;
     int64_t *num_items;
     int64_t tile;
+    int32_t tile_shift;   // tile = 2^tile_shift
     int32_t mode;
     int32_t need_keys;
 };
@@ -72,11 +73,11 @@ int64_t seg_max_items(int64_t n, int64_t m, int64_t tile) {
 }
 
 // ------------------------------------------------------------------ setup --
-// One workgroup of 1024 threads.  Shapes are processed in chunks of 16384
-// rows (16 consecutive rows per thread); the per-thread sums of row sizes and
-// item counts are scanned with wave shuffles and LDS, carried across chunks.
+// One workgroup of 1024 threads.  Shapes are processed in chunks of 4096 rows
+// (4 consecutive rows per thread); the per-thread sums of row sizes and item
+// counts are scanned with wave shuffles and LDS, carried across chunks.
 constexpr int kSetupThreads = 1024;
-constexpr int kSetupPer = 16;
+constexpr int kSetupPer = 4;
 
 __device__ __forceinline__ int64_t block_exclusive_scan_1024(int64_t v, int64_t *lds16,
                                                              int64_t *total) {
@@ -131,7 +132,7 @@ __global__ __launch_bounds__(kSetupThreads) void seg_setup_kernel(SegArgs a) {
 #pragma unroll
             for (int j = 0; j < kSetupPer; ++j) {
                 const int64_t ak = o & ~int64_t{3};
-                nitems[j] = s[j] > 0 ? ceil_div(o + s[j] - ak, a.tile) : 0;
+                nitems[j] = s[j] > 0 ? ((o + s[j] - ak + a.tile - 1) >> a.tile_shift) : 0;
                 sum_it += nitems[j];
                 o += s[j];
             }
@@ -186,23 +187,28 @@ __global__ __launch_bounds__(256) void seg_items_kernel(SegArgs a) {
 }
 
 // ------------------------------------------------------------------ count --
+// One workgroup (4 waves) per item, workgroups striding over the items; the
+// waves split the item's 1024-element chunks and add their counts in LDS.
 template <class Pred>
 __global__ __launch_bounds__(256) void seg_count_kernel(SegArgs a, Pred pred) {
     using WT = Tile<kWave, 4, 4>;   // one wave, 1024 elements per chunk
+    __shared__ uint32_t part[4];
     const int lane = threadIdx.x & (kWave - 1);
+    const int wave = wave_id();
     const int64_t nitems = *a.num_items;
-    const int64_t w0 = static_cast<int64_t>(blockIdx.x) * 4 + wave_id();
-    const int64_t nw = static_cast<int64_t>(gridDim.x) * 4;
-    for (int64_t it = w0; it < nitems; it += nw) {
+    for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
         const SegItem d = a.items[it];
         if (a.mode == IXP_MODE_PARTITION && (d.kind & 1)) continue;   // counted in place
         uint32_t cnt = 0;
-        for (int64_t b = d.base; b < d.hi; b += WT::kSize) {
+        for (int64_t b = d.base + static_cast<int64_t>(wave) * WT::kSize; b < d.hi; b += 4 * WT::kSize) {
             WT chunk;
             chunk.load(a.keys, a.n, b, d.lo, d.hi, pred, !Pred::kUsesFlags, 0, lane);
             cnt += chunk.wave_count();
         }
-        if (lane == 0) a.items[it].count = cnt;
+        if (lane == 0) part[wave] = cnt;
+        __syncthreads();
+        if (threadIdx.x == 0) a.items[it].count = part[0] + part[1] + part[2] + part[3];
+        __syncthreads();
     }
 }
 
@@ -267,12 +273,19 @@ __global__ __launch_bounds__(256) void seg_row_totals_kernel(SegArgs a) {
 }
 
 // ------------------------------------------------------------------- main --
+// Persistent workgroups.  Wave 0 prefetches the next work item -- its queue
+// ticket and its 48-byte descriptor, one 8-byte word per lane -- while the
+// workgroup processes the current one, so the queue and descriptor latencies
+// overlap the item's loads and stores.
 template <int BLOCK, int ROWS, class Pred, int MODE, class Idx>
 __global__ __launch_bounds__(BLOCK) void seg_main_kernel(SegArgs a, Pred pred) {
     using T = Tile<BLOCK, ROWS, 4>;
     constexpr int kTile = T::kSize;
+    constexpr int kWords = sizeof(SegItem) / 8;
+    static_assert(sizeof(SegItem) % 8 == 0 && kWords <= kWave, "descriptor words");
     __shared__ uint32_t stage[kTile];
     __shared__ uint32_t wtot[T::kWaves];
+    __shared__ int64_t sh_desc[kWords];
     __shared__ int64_t sh_item;
 
     const int tid = threadIdx.x;
@@ -280,17 +293,38 @@ __global__ __launch_bounds__(BLOCK) void seg_main_kernel(SegArgs a, Pred pred) {
     const int lane = tid & (kWave - 1);
     const int64_t nitems = *a.num_items;
     Idx *out_idx = static_cast<Idx *>(a.out_idx);
+    const int64_t *words = reinterpret_cast<const int64_t *>(a.items);
+
+    int64_t next = 0, next_word = 0;
+    auto prefetch = [&]() {
+        uint32_t tk = 0;
+        if (lane == 0) tk = atomicAdd(a.ticket, 1u);
+        next = __builtin_amdgcn_readfirstlane(static_cast<int>(tk));
+        if (lane < kWords && next < nitems) next_word = words[next * kWords + lane];
+    };
+    if (wave == 0) prefetch();
 
     for (;;) {
-        if (tid == 0) sh_item = atomicAdd(a.ticket, 1u);
+        if (wave == 0) {
+            if (lane < kWords) sh_desc[lane] = next_word;
+            if (lane == 0) sh_item = next;
+        }
         __syncthreads();
         const int64_t it = sh_item;
         if (it >= nitems) break;
-        const SegItem d = a.items[it];
+        SegItem d;
+        {
+            int64_t w[kWords];
+#pragma unroll
+            for (int k = 0; k < kWords; ++k) w[k] = sh_desc[k];
+            __builtin_memcpy(&d, w, sizeof(SegItem));
+        }
+        if (wave == 0) prefetch();   // overlaps with this item
         const int64_t lo = d.lo, hi = d.hi, base = d.base;
 
         T tile;
-        tile.load(a.keys, a.n, base, lo, hi, pred, a.need_keys != 0, wave, lane);
+        if (T::wave_live(base, lo, hi, wave))   // waves past a short item load nothing
+            tile.load(a.keys, a.n, base, lo, hi, pred, a.need_keys != 0, wave, lane);
         tile.wave_ranks();
         const uint32_t tcount = tile.block_ranks(wtot, wave, lane);
 
@@ -302,6 +336,7 @@ __global__ __launch_bounds__(BLOCK) void seg_main_kernel(SegArgs a, Pred pred) {
         }
         const bool first = (d.kind & 2) != 0;
 
+        const int32_t l0 = static_cast<int32_t>(base - lo) + wave * T::kPerWave + lane * 4;
 #pragma unroll
         for (int r = 0; r < ROWS; ++r) {
             const int64_t p0 = T::pos(base, wave, r, lane, 0);
@@ -311,12 +346,12 @@ __global__ __launch_bounds__(BLOCK) void seg_main_kernel(SegArgs a, Pred pred) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const uint32_t rt = tile.rank[r][q];
-                const int64_t p = p0 + q;
-                const uint32_t rf = static_cast<uint32_t>(p - lo) - rt;
+                const int32_t l = l0 + r * (kWave * 4) + q;   // offset from lo
+                const uint32_t rf = static_cast<uint32_t>(l) - rt;
                 const bool f = tile.flag(r, q);
                 const bool ok = tile.valid(r, q);
                 vm |= static_cast<uint32_t>(ok) << q;
-                fl |= static_cast<uint32_t>(first && p == lo) << (8 * q);
+                fl |= static_cast<uint32_t>(first && l == 0) << (8 * q);
                 if (MODE == IXP_MODE_PARTITION)
                     v[q] = static_cast<Idx>(f ? tbase + rt : fbase + rf);
                 else
@@ -347,7 +382,7 @@ __global__ __launch_bounds__(BLOCK) void seg_main_kernel(SegArgs a, Pred pred) {
                 if (dst >= 0 && dst < a.n) stream_store(a.out_keys + dst, stage[s]);
             }
         }
-        __syncthreads();   // LDS and sh_item are reused by the next item
+        __syncthreads();   // LDS is reused by the next item
     }
 }
 
@@ -357,10 +392,11 @@ struct SegGeom {
     int64_t tile() const { return static_cast<int64_t>(block) * rows * 4; }
 };
 
+// Every supported tile is a power of two (block and rows are).
 bool geom_supported(const SegGeom &g) {
     const bool b = g.block == 256 || g.block == 512 || g.block == 1024;
     const bool r = g.rows == 2 || g.rows == 4 || g.rows == 8;
-    return b && r && g.tile() <= 16384 && g.wgs_per_cu >= 1 && g.wgs_per_cu <= 16;
+    return b && r && g.tile() <= 16384 && g.wgs_per_cu >= 1 && g.wgs_per_cu <= 64;
 }
 
 SegGeom geom_from(const ixp_tuning *t) {
@@ -487,6 +523,8 @@ int prepare(const void *keys, int32_t key_t, int64_t n, const int64_t *d_shape, 
     a->items = reinterpret_cast<SegItem *>(w + kSegHeader + 2 * rows_bytes);
     a->max_items = seg_max_items(n, m, g.tile());
     a->tile = g.tile();
+    a->tile_shift = 0;
+    while ((int64_t{1} << a->tile_shift) < a->tile) ++a->tile_shift;
     a->mode = mode;
     a->need_keys = need_keys ? 1 : 0;
     return IXP_OK;
@@ -549,10 +587,15 @@ extern "C" int ixp_tune_segmented(const void *keys, int32_t key_t, int64_t n,
     float best_t = -1.f;
     int rc_out = IXP_EUNSUPPORTED;
     for (const auto &c : kCands) {
-        for (int wpc = 0; wpc <= 1; ++wpc) {
+        // persistent grids (as many workgroups per CU as fit, or one fewer),
+        // and oversubscribed grids of 16 or 64 per CU, where most workgroups
+        // take a single item and the hardware overlaps them
+        for (int wpc = 0; wpc < 4; ++wpc) {
             ixp_tuning t{c[0], c[1], 0, 0};
             SegGeom g = geom_from(&t);
             if (wpc == 1) g.wgs_per_cu = g.wgs_per_cu > 1 ? g.wgs_per_cu - 1 : 1;
+            if (wpc == 2) g.wgs_per_cu = 16;
+            if (wpc == 3) g.wgs_per_cu = 64;
             t.wgs_per_cu = g.wgs_per_cu;
             SegArgs a;
             HostPred hp;

@@ -170,3 +170,29 @@ def test_filtpart_checks_gpu_partition_output():
         ok, oi, sp = P.partition(xt, gp, mode=mode, idx_dtype=torch.int32)
         v = P.verdicts(P.check_props(oi, P.FILTPART, fp=P.FiltPartArgs(xt, ok, gp, sp, mode)))
         assert v[4] == (1, -1, 0)
+
+
+def test_bucketed_and_fallback_paths():
+    """Arrays of 2^16 or more entries whose Rcd spans at most 4096 buckets of
+    2^20 values take the bucketed Inj/Bij path; wider co-domains fall back to
+    the global bitmap.  Both must give the oracle's verdicts."""
+    g = np.random.default_rng(77)
+    n = 200_003
+    # int32 values, bucketed, with repeats and values outside Rcd
+    x = g.integers(-1000, 3 * n, n).astype(np.int32)
+    both(x, ALL4, 0, 3 * n, 5, 3 * n - 5, dtype=np.int32)
+    # a permutation with its Rcd shifted: Img is a strict sub-range
+    p = W.permutation(n, 78) + 10_000_000
+    both(p, ALL4, 10_000_000, 10_000_000 + n, 10_000_000, 10_000_000 + n)
+    both(p, P.INJ | P.BIJ, 9_000_000, 12_000_000, 10_000_000, 10_000_000 + n)
+    # fewer than 2^16 entries: the global-bitmap path
+    y = g.integers(0, 1 << 26, (1 << 16) - 1)
+    y[500] = y[77]
+    both(y, ALL4, 0, 1 << 26, 0, 1 << 26)
+    # a co-domain of 2^33 values spans more than 4096 buckets: global bitmap
+    y = g.integers(0, 1 << 33, 1 << 16)
+    y[900] = y[800]
+    both(y, P.INJ | P.RANGE, 0, 1 << 33)
+    # a bucket boundary: values just around multiples of 2^20
+    z = (np.arange(n) // 7) * (1 << 20) + (np.arange(n) % 7) - 3
+    both(z, P.INJ | P.RANGE, -3, int(z.max()) + 1)

@@ -66,7 +66,7 @@ def test_random_shapes_with_empty_rows(mode, idx_dtype):
 
 
 @pytest.mark.parametrize("tune", [(256, 2), (256, 4), (256, 8), (512, 2), (512, 4), (512, 8),
-                                  (1024, 2), (1024, 4), (512, 4, 1)])
+                                  (1024, 2), (1024, 4), (512, 4, 1), (256, 2, 64)])
 def test_every_tiling_matches(tune):
     shape = W.segment_sizes(400, 11, median_log2=11, sigma_log2=2.0, empty_frac=0.1)
     keys = W.int_keys(int(shape.sum()), 12)
