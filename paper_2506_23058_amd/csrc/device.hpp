@@ -430,4 +430,31 @@ __device__ __forceinline__ void store_idx_group(Idx *out, int64_t p0, const Idx 
     }
 }
 
+// Writes the run stage[src, src+len) to out[g, g+len): a head of up to three
+// elements up to the next 16-byte boundary of out + g, 16-byte stores for the
+// aligned body, then the tail.
+template <int BLOCK>
+__device__ __forceinline__ void write_run(const uint32_t *stage, uint32_t src, uint32_t len, int64_t g,
+                                          uint32_t *out, int64_t n, int tid) {
+    if (len == 0) return;
+    // elements until out + g reaches a 16-byte boundary (out is 4-byte aligned)
+    const uint32_t mis = static_cast<uint32_t>((reinterpret_cast<uintptr_t>(out + g) >> 2) & 3);
+    const uint32_t to16 = (4 - mis) & 3;
+    const uint32_t head = to16 < len ? to16 : len;
+    const uint32_t groups = (len - head) / 4;
+    const uint32_t tail = len - head - 4 * groups;
+    for (uint32_t j = tid; j < groups; j += BLOCK) {
+        const uint32_t s = src + head + 4 * j;
+        u32x4 v;
+        v.x = stage[s]; v.y = stage[s + 1]; v.z = stage[s + 2]; v.w = stage[s + 3];
+        const int64_t d = g + head + 4 * static_cast<int64_t>(j);
+        if (d + 4 <= n) stream_store(reinterpret_cast<u32x4 *>(out + d), v);
+    }
+    if (static_cast<uint32_t>(tid) < head && g + tid < n) stream_store(out + g + tid, stage[src + tid]);
+    if (static_cast<uint32_t>(tid) < tail) {
+        const uint32_t k = head + 4 * groups + tid;
+        if (g + k < n) stream_store(out + g + k, stage[src + k]);
+    }
+}
+
 }  // namespace ixp

@@ -36,13 +36,29 @@ namespace {
 constexpr size_t kWsHeader = 256;   // ticket (u32), error word (i32), padding
 
 // Tile geometry.  Partition: 256 threads x 4 rows x 4 = 4096 elements per
-// tile (the count kernel uses the same tiles).  Filter: 512 x 4 x 4 = 8192, so
-// that tiles start slowly enough for one look-back round to reach a published
-// inclusive prefix.  Unaligned buffers use one-element groups (VEC = 1).
+// tile (the count kernel uses the same tiles).  Filter: 1024 x 4 x 4 = 16384:
+// every filter tile takes one ticket from a single counter, whose atomics
+// serialise (~10 ns each), and its look-back must reach a published inclusive
+// prefix in one round, so fewer, larger tiles go faster.  Unaligned buffers
+// use one-element groups (VEC = 1).
+#ifndef IXP_FLAT_PART_BLOCK
+#define IXP_FLAT_PART_BLOCK 256
+#endif
+#ifndef IXP_FLAT_PART_ROWS
+#define IXP_FLAT_PART_ROWS 4
+#endif
+#ifndef IXP_FLAT_FILT_BLOCK
+#define IXP_FLAT_FILT_BLOCK 1024
+#endif
+#ifndef IXP_VEC_RUNS
+#define IXP_VEC_RUNS 1
+#endif
+
 template <int MODE, int VEC>
 struct FlatCfg {
-    static constexpr int kBlock = MODE == IXP_MODE_PARTITION ? 256 : 512;
-    static constexpr int kRows = VEC == 4 ? 4 : 16;
+    static constexpr int kBlock = MODE == IXP_MODE_PARTITION ? IXP_FLAT_PART_BLOCK : IXP_FLAT_FILT_BLOCK;
+    static constexpr int kRows = VEC == 4 ? (MODE == IXP_MODE_PARTITION ? IXP_FLAT_PART_ROWS : 4)
+                                          : 16 * (MODE == IXP_MODE_PARTITION ? IXP_FLAT_PART_ROWS : 4) / 4;
     using T = Tile<kBlock, kRows, VEC>;
     static constexpr int kTile = T::kSize;
 };
@@ -235,11 +251,17 @@ __global__ __launch_bounds__((FlatCfg<MODE, VEC>::kBlock)) void flat_scan_kernel
     if (a.out_keys) {
         __syncthreads();
         const int64_t nvalid = hi - lo;
+#if IXP_VEC_RUNS
+        write_run<kBlock>(stage, 0, tcount, excl, a.out_keys, a.n, tid);
+        if (MODE == IXP_MODE_PARTITION)
+            write_run<kBlock>(stage, tcount, static_cast<uint32_t>(nvalid) - tcount, false_base, a.out_keys, a.n, tid);
+#else
         const int64_t nout = MODE == IXP_MODE_PARTITION ? nvalid : static_cast<int64_t>(tcount);
         for (int64_t s = tid; s < nout; s += kBlock) {
             const int64_t dst = s < tcount ? excl + s : false_base + (s - tcount);
             if (dst < a.n) stream_store(a.out_keys + dst, stage[s]);
         }
+#endif
     }
 }
 

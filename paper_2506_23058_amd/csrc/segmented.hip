@@ -16,13 +16,14 @@
 //   [A_k + j*TILE, A_k + (j+1)*TILE) ∩ [o_k, o_k + s_k),   A_k = o_k rounded down to 4.
 // Kernels (all stream-ordered, capturable in one HIP graph):
 //   seg_setup -- one workgroup: validates the shape, scans it into row offsets
-//                and item offsets, resets the work queue;
-//   seg_items -- one thread per row writes the row's item descriptors;
-//   seg_count -- one wave per item counts the trues of the items whose row
-//                spans several items (partition) or of every item (filter);
-//   seg_scan  -- per row (partition) / over all items (filter): turns item
-//                counts into output bases and writes T_k of multi-item rows;
-//   seg_main  -- persistent workgroups pull items from an atomic queue; each
+//                and item offsets;
+//   seg_items -- item descriptors, written in parallel over items;
+//   seg_count -- one wave per 1024-element chunk counts the trues of the items
+//                whose row spans several items (partition) or of every item
+//                (filter) into a dense array of item counts;
+//   seg_scan_items / seg_item_bases -- one scan of all item counts, then per
+//                item its output bases and T_k of its row;
+//   seg_main  -- persistent workgroups take items round-robin; each
 //                loads its item, ranks the trues by ballot/mbcnt, writes the
 //                indices and descriptor bytes in input order and the keys,
 //                staged in LDS, as two contiguous runs.  A row that fits one
@@ -33,9 +34,9 @@
 namespace ixp {
 namespace {
 
-constexpr size_t kSegHeader = 256;   // ticket u32 @0, error i32 @4, item count i64 @8
+constexpr size_t kSegHeader = 256;   // error i32 @4, item count i64 @8
 
-// Per-item descriptor written by seg_setup and completed by seg_scan.
+// Per-item descriptor written by seg_items and completed by seg_item_bases.
 struct alignas(16) SegItem {
     int64_t lo, hi;      // valid positions [lo, hi)
     int64_t base;        // first position of the item's 4-aligned tile
@@ -43,7 +44,7 @@ struct alignas(16) SegItem {
     int64_t fbase;       // output position of the item's first false
     int32_t row;         // row k
     int32_t kind;        // bit 0: row fits one item; bit 1: first item of its row
-    int64_t count;       // trues in the item (counted items only)
+    int64_t spare;       // pads the descriptor to six 8-byte words
 };
 
 struct SegArgs {
@@ -58,8 +59,9 @@ struct SegArgs {
     int64_t *offsets;     // [m + 1] row offsets
     int64_t *item_off;    // [m + 1] first item of each row
     SegItem *items;       // [max_items]
+    int64_t *prefix;      // [max_items + 1] exclusive scan of item counts
+    unsigned long long *counts;   // [max_items] trues per counted item
     int64_t max_items;
-    uint32_t *ticket;
     int32_t *err;
     int64_t *num_items;
     int64_t tile;
@@ -159,83 +161,82 @@ __global__ __launch_bounds__(kSetupThreads) void seg_setup_kernel(SegArgs a) {
         a.offsets[a.m] = carry_off;
         a.item_off[a.m] = carry_items;
         *a.num_items = ok ? carry_items : 0;
-        *a.ticket = 0;
         *a.err = ok ? 0 : kErrShape;
     }
 }
 
-// One thread per row writes the row's item descriptors.
+// One workgroup per 256 rows: the rows' offsets go to LDS, then the
+// workgroup's threads write the rows' item descriptors in parallel (an item
+// finds its row by binary search in LDS), so a row of many items costs no
+// more than many rows of one item.  Empty rows get T_k = 0 here.
 __global__ __launch_bounds__(256) void seg_items_kernel(SegArgs a) {
-    const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (k >= a.m || *a.num_items == 0) return;
-    const int64_t o = a.offsets[k], e = a.offsets[k + 1];
-    const int64_t i0 = a.item_off[k], i1 = a.item_off[k + 1];
-    const int64_t ak = o & ~int64_t{3};
-    for (int64_t idx = i0; idx < i1; ++idx) {
+    __shared__ int64_t s_off[257], s_it[257];
+    if (*a.err != 0) return;
+    const int64_t r0 = static_cast<int64_t>(blockIdx.x) * 256;
+    const int nr = static_cast<int>(a.m - r0 < 256 ? a.m - r0 : 256);
+    for (int j = threadIdx.x; j <= nr; j += blockDim.x) {
+        s_off[j] = a.offsets[r0 + j];
+        s_it[j] = a.item_off[r0 + j];
+    }
+    __syncthreads();
+    if (static_cast<int>(threadIdx.x) < nr && s_it[threadIdx.x] == s_it[threadIdx.x + 1] && a.seg_split)
+        a.seg_split[r0 + threadIdx.x] = 0;   // empty row
+    for (int64_t idx = s_it[0] + threadIdx.x; idx < s_it[nr]; idx += blockDim.x) {
+        int lo = 0, hi = nr - 1;   // last row j with s_it[j] <= idx
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_it[mid] <= idx) lo = mid;
+            else hi = mid - 1;
+        }
+        const int64_t o = s_off[lo], e = s_off[lo + 1];
+        const int64_t i0 = s_it[lo], i1 = s_it[lo + 1];
         const int64_t q = idx - i0;
+        const int64_t ak = o & ~int64_t{3};
         SegItem d;
         d.base = ak + q * a.tile;
         d.lo = d.base > o ? d.base : o;
         d.hi = d.base + a.tile < e ? d.base + a.tile : e;
         d.tbase = 0;
         d.fbase = 0;
-        d.row = static_cast<int32_t>(k);
+        d.row = static_cast<int32_t>(r0 + lo);
         d.kind = (i1 - i0 == 1 ? 1 : 0) | (q == 0 ? 2 : 0);
-        d.count = 0;
+        d.spare = 0;
         a.items[idx] = d;
+        a.counts[idx] = 0;
     }
 }
 
 // ------------------------------------------------------------------ count --
-// One workgroup (4 waves) per item, workgroups striding over the items; the
-// waves split the item's 1024-element chunks and add their counts in LDS.
+// One wave per 1024-element chunk of a counted item (items of rows that span
+// several items in partition mode, every item in filter mode); each wave adds
+// its chunk's trues to the item's count.  Waves of one item hit one address
+// at most tile/1024 times, so the atomics do not queue.
 template <class Pred>
 __global__ __launch_bounds__(256) void seg_count_kernel(SegArgs a, Pred pred) {
-    using WT = Tile<kWave, 4, 4>;   // one wave, 1024 elements per chunk
-    __shared__ uint32_t part[4];
+    using WT = Tile<kWave, 4, 4>;   // one wave, 1024 elements
     const int lane = threadIdx.x & (kWave - 1);
-    const int wave = wave_id();
     const int64_t nitems = *a.num_items;
-    for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
-        const SegItem d = a.items[it];
+    const int cshift = a.tile_shift - 10;   // chunks per item = tile / 1024
+    const int64_t work = nitems << cshift;
+    const int64_t nw = static_cast<int64_t>(gridDim.x) * 4;
+    for (int64_t w = static_cast<int64_t>(blockIdx.x) * 4 + wave_id(); w < work; w += nw) {
+        const int64_t it = w >> cshift;
+        const int64_t c = w & ((int64_t{1} << cshift) - 1);
+        const SegItem &d = a.items[it];
         if (a.mode == IXP_MODE_PARTITION && (d.kind & 1)) continue;   // counted in place
-        uint32_t cnt = 0;
-        for (int64_t b = d.base + static_cast<int64_t>(wave) * WT::kSize; b < d.hi; b += 4 * WT::kSize) {
-            WT chunk;
-            chunk.load(a.keys, a.n, b, d.lo, d.hi, pred, !Pred::kUsesFlags, 0, lane);
-            cnt += chunk.wave_count();
-        }
-        if (lane == 0) part[wave] = cnt;
-        __syncthreads();
-        if (threadIdx.x == 0) a.items[it].count = part[0] + part[1] + part[2] + part[3];
-        __syncthreads();
+        const int64_t b = d.base + (c << 10);
+        if (b >= d.hi) continue;
+        WT chunk;
+        chunk.load(a.keys, a.n, b, d.lo, d.hi, pred, !Pred::kUsesFlags, 0, lane);
+        const uint32_t cnt = chunk.wave_count();
+        if (lane == 0 && cnt) atomicAdd(a.counts + it, static_cast<unsigned long long>(cnt));
     }
 }
 
 // ------------------------------------------------------------------- scan --
-// Partition: one thread per row; rows of several items get their items'
-// output bases and T_k.
-__global__ __launch_bounds__(256) void seg_scan_rows_kernel(SegArgs a) {
-    const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (k >= a.m || *a.err != 0) return;
-    const int64_t i0 = a.item_off[k], i1 = a.item_off[k + 1];
-    if (i1 == i0 && a.seg_split) a.seg_split[k] = 0;   // empty row
-    if (i1 - i0 <= 1) return;   // one-item rows are finished by the main kernel
-    const int64_t ok = a.offsets[k];
-    int64_t tk = 0;
-    for (int64_t i = i0; i < i1; ++i) tk += a.items[i].count;
-    int64_t before = 0;
-    for (int64_t i = i0; i < i1; ++i) {
-        const int64_t lo = a.items[i].lo;
-        a.items[i].tbase = ok + before;
-        a.items[i].fbase = ok + tk + (lo - ok - before);
-        before += a.items[i].count;
-    }
-    if (a.seg_split) a.seg_split[k] = tk;
-}
-
-// Filter: one workgroup scans all item counts (chunks of 1024 * 8 items) into
-// global output bases; then one thread per row sums its T_k.
+// One workgroup scans all item counts (chunks of 1024 * 8 items) into
+// prefix[0..num_items]; items of rows counted in place (partition, one item)
+// count 0.
 __global__ __launch_bounds__(1024) void seg_scan_items_kernel(SegArgs a) {
     __shared__ int64_t lds[16];
     const int64_t nitems = *a.num_items;
@@ -247,36 +248,54 @@ __global__ __launch_bounds__(1024) void seg_scan_items_kernel(SegArgs a) {
         int64_t sum = 0;
 #pragma unroll
         for (int j = 0; j < kPer; ++j) {
-            v[j] = i0 + j < nitems ? a.items[i0 + j].count : 0;
+            v[j] = i0 + j < nitems ? static_cast<int64_t>(a.counts[i0 + j]) : 0;
             sum += v[j];
         }
         int64_t tot;
         int64_t acc = carry + block_exclusive_scan_1024(sum, lds, &tot);
 #pragma unroll
         for (int j = 0; j < kPer; ++j) {
-            if (i0 + j < nitems) {
-                a.items[i0 + j].tbase = acc;
-                a.items[i0 + j].fbase = 0;
-            }
+            if (i0 + j < nitems) a.prefix[i0 + j] = acc;
             acc += v[j];
         }
         carry += tot;
     }
+    if (threadIdx.x == 0) a.prefix[nitems] = carry;
 }
 
-__global__ __launch_bounds__(256) void seg_row_totals_kernel(SegArgs a) {
-    const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (k >= a.m || *a.err != 0 || !a.seg_split) return;
-    int64_t tk = 0;
-    for (int64_t i = a.item_off[k]; i < a.item_off[k + 1]; ++i) tk += a.items[i].count;
-    a.seg_split[k] = tk;
+// One thread per item: output bases from the prefix.  Partition: a row of
+// several items gets o_k + (trues before the item in the row) for its trues
+// and o_k + T_k + (falses before the item in the row) for its falses; the
+// row's first item writes T_k.  Filter: kept elements of all rows are packed,
+// so the base is the global prefix; the first item writes the row's T_k.
+__global__ __launch_bounds__(256) void seg_item_bases_kernel(SegArgs a) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t nitems = *a.num_items;
+    if (i >= nitems) return;
+    const SegItem d = a.items[i];
+    const int64_t k = d.row;
+    const int64_t i0 = a.item_off[k], i1 = a.item_off[k + 1];
+    if (a.mode == IXP_MODE_PARTITION) {
+        if (d.kind & 1) return;   // one-item row: finished by the main kernel
+        const int64_t ok = a.offsets[k];
+        const int64_t p0 = a.prefix[i0];
+        const int64_t before = a.prefix[i] - p0;
+        const int64_t tk = a.prefix[i1] - p0;
+        a.items[i].tbase = ok + before;
+        a.items[i].fbase = ok + tk + (d.lo - ok - before);
+        if (i == i0 && a.seg_split) a.seg_split[k] = tk;
+    } else {
+        a.items[i].tbase = a.prefix[i];
+        a.items[i].fbase = 0;
+        if (i == i0 && a.seg_split) a.seg_split[k] = a.prefix[i1] - a.prefix[i0];
+    }
 }
 
 // ------------------------------------------------------------------- main --
-// Persistent workgroups.  Wave 0 prefetches the next work item -- its queue
-// ticket and its 48-byte descriptor, one 8-byte word per lane -- while the
-// workgroup processes the current one, so the queue and descriptor latencies
-// overlap the item's loads and stores.
+// Persistent workgroups take items round-robin (item = blockIdx.x + k *
+// gridDim.x: no shared queue counter, whose serialised atomics would cost
+// ~10 ns per item).  Wave 0 prefetches the next item's 48-byte descriptor,
+// one 8-byte word per lane, while the workgroup processes the current one.
 template <int BLOCK, int ROWS, class Pred, int MODE, class Idx>
 __global__ __launch_bounds__(BLOCK) void seg_main_kernel(SegArgs a, Pred pred) {
     using T = Tile<BLOCK, ROWS, 4>;
@@ -295,11 +314,8 @@ __global__ __launch_bounds__(BLOCK) void seg_main_kernel(SegArgs a, Pred pred) {
     Idx *out_idx = static_cast<Idx *>(a.out_idx);
     const int64_t *words = reinterpret_cast<const int64_t *>(a.items);
 
-    int64_t next = 0, next_word = 0;
+    int64_t next = blockIdx.x, next_word = 0;
     auto prefetch = [&]() {
-        uint32_t tk = 0;
-        if (lane == 0) tk = atomicAdd(a.ticket, 1u);
-        next = __builtin_amdgcn_readfirstlane(static_cast<int>(tk));
         if (lane < kWords && next < nitems) next_word = words[next * kWords + lane];
     };
     if (wave == 0) prefetch();
@@ -319,7 +335,10 @@ __global__ __launch_bounds__(BLOCK) void seg_main_kernel(SegArgs a, Pred pred) {
             for (int k = 0; k < kWords; ++k) w[k] = sh_desc[k];
             __builtin_memcpy(&d, w, sizeof(SegItem));
         }
-        if (wave == 0) prefetch();   // overlaps with this item
+        if (wave == 0) {   // overlaps with this item
+            next = it + gridDim.x;
+            prefetch();
+        }
         const int64_t lo = d.lo, hi = d.hi, base = d.base;
 
         T tile;
@@ -375,12 +394,10 @@ __global__ __launch_bounds__(BLOCK) void seg_main_kernel(SegArgs a, Pred pred) {
         }
         if (a.out_keys) {
             __syncthreads();
-            const int64_t nvalid = hi - lo;
-            const int64_t nout = MODE == IXP_MODE_PARTITION ? nvalid : static_cast<int64_t>(tcount);
-            for (int64_t s = tid; s < nout; s += BLOCK) {
-                const int64_t dst = s < tcount ? tbase + s : fbase + (s - tcount);
-                if (dst >= 0 && dst < a.n) stream_store(a.out_keys + dst, stage[s]);
-            }
+            const uint32_t nvalid = static_cast<uint32_t>(hi - lo);
+            write_run<BLOCK>(stage, 0, tcount, tbase, a.out_keys, a.n, tid);
+            if (MODE == IXP_MODE_PARTITION)
+                write_run<BLOCK>(stage, tcount, nvalid - tcount, fbase, a.out_keys, a.n, tid);
         }
         __syncthreads();   // LDS is reused by the next item
     }
@@ -462,15 +479,15 @@ int launch_all(const SegArgs &a, const Pred &p, const SegGeom &g, int mode, int 
     IXP_LAUNCH("seg_items", seg_items_kernel, dim3(rblocks), dim3(256), 0, st, a);
     if (launch_status() != IXP_OK) return IXP_EHIP;
     const int cus = device_cus();
-    IXP_LAUNCH("seg_count", (seg_count_kernel<Pred>), dim3(cus * 8), dim3(256), 0, st, a, p);
-    if (launch_status() != IXP_OK) return IXP_EHIP;
-    if (mode == IXP_MODE_PARTITION) {
-        IXP_LAUNCH("seg_scan_rows", seg_scan_rows_kernel, dim3(rblocks), dim3(256), 0, st, a);
-    } else {
-        IXP_LAUNCH("seg_scan_items", seg_scan_items_kernel, dim3(1), dim3(1024), 0, st, a);
-        if (launch_status() != IXP_OK) return IXP_EHIP;
-        IXP_LAUNCH("seg_row_totals", seg_row_totals_kernel, dim3(rblocks), dim3(256), 0, st, a);
-    }
+    // one wave per chunk of the largest possible item list, capped
+    const int64_t chunk_waves = a.max_items * (a.tile >> 10);
+    const int64_t cblocks = ceil_div(chunk_waves, 4) < static_cast<int64_t>(cus) * 64
+                                ? ceil_div(chunk_waves, 4) : static_cast<int64_t>(cus) * 64;
+    IXP_LAUNCH("seg_count", (seg_count_kernel<Pred>), dim3(static_cast<uint32_t>(cblocks)), dim3(256), 0,
+               st, a, p);
+    IXP_LAUNCH("seg_scan_items", seg_scan_items_kernel, dim3(1), dim3(1024), 0, st, a);
+    const uint32_t iblocks = static_cast<uint32_t>(ceil_div(a.max_items, 256));
+    IXP_LAUNCH("seg_item_bases", seg_item_bases_kernel, dim3(iblocks), dim3(256), 0, st, a);
     if (launch_status() != IXP_OK) return IXP_EHIP;
     return launch_main(a, p, g, mode, idx_t, st);
 }
@@ -478,7 +495,8 @@ int launch_all(const SegArgs &a, const Pred &p, const SegGeom &g, int mode, int 
 size_t seg_workspace(int64_t n, int64_t m, const SegGeom &g) {
     const int64_t mi = seg_max_items(n, m, g.tile());
     return kSegHeader + round_up(static_cast<size_t>(m + 1) * 8, 256) * 2 +
-           static_cast<size_t>(mi) * sizeof(SegItem);
+           round_up(static_cast<size_t>(mi) * sizeof(SegItem), 256) +
+           round_up(static_cast<size_t>(mi + 1) * 8, 256) + static_cast<size_t>(mi) * 8;
 }
 
 int prepare(const void *keys, int32_t key_t, int64_t n, const int64_t *d_shape, int64_t m,
@@ -515,13 +533,16 @@ int prepare(const void *keys, int32_t key_t, int64_t n, const int64_t *d_shape, 
     a->out_idx = out_idx;
     a->seg_split = d_seg_split;
     a->flags_out = d_flags_out;
-    a->ticket = reinterpret_cast<uint32_t *>(w);
     a->err = reinterpret_cast<int32_t *>(w + 4);
     a->num_items = reinterpret_cast<int64_t *>(w + 8);
     a->offsets = reinterpret_cast<int64_t *>(w + kSegHeader);
     a->item_off = reinterpret_cast<int64_t *>(w + kSegHeader + rows_bytes);
     a->items = reinterpret_cast<SegItem *>(w + kSegHeader + 2 * rows_bytes);
     a->max_items = seg_max_items(n, m, g.tile());
+    a->prefix = reinterpret_cast<int64_t *>(
+        w + kSegHeader + 2 * rows_bytes + round_up(static_cast<size_t>(a->max_items) * sizeof(SegItem), 256));
+    a->counts = reinterpret_cast<unsigned long long *>(
+        reinterpret_cast<char *>(a->prefix) + round_up(static_cast<size_t>(a->max_items + 1) * 8, 256));
     a->tile = g.tile();
     a->tile_shift = 0;
     while ((int64_t{1} << a->tile_shift) < a->tile) ++a->tile_shift;

@@ -145,3 +145,17 @@ def test_deterministic_repeat():
     a = P.partition(kt, P.Pred.mod_eq(3, 0))
     b = P.partition(kt, P.Pred.mod_eq(3, 0))
     assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]) and torch.equal(a[2], b[2])
+
+
+def test_unaligned_output_keys():
+    """Output keys 4-byte but not 16-byte aligned: the run writer's head and
+    tail handle the misalignment."""
+    keys = W.int_keys(100_001, 14)
+    kt = torch.from_numpy(keys).to(DEV)
+    ys, idx, t = O.partition2(keys, O.Pred.mod_eq(2, 0))
+    big = torch.zeros(len(keys) + 4, dtype=torch.int32, device=DEV)
+    for off in (1, 2, 3):
+        out = big[off:off + len(keys)]
+        assert out.data_ptr() % 16 != 0
+        P.partition(kt, P.Pred.mod_eq(2, 0), out_keys=out)
+        assert np.array_equal(out.cpu().numpy(), ys)
