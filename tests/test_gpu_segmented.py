@@ -143,3 +143,33 @@ def test_autotuner_returns_a_valid_tiling():
     best, ms = P.tune_segmented(kt, st, P.Pred.mod_eq(3, 0), reps=2)
     assert best[0] in (256, 512, 1024) and best[1] in (2, 4, 8) and ms > 0
     run_both(keys, shape, tune=best)
+
+
+@pytest.mark.parametrize("tune", [(256, 2), (512, 2), (512, 4), (1024, 4)])
+def test_many_rows_per_tile_with_empty_rows(tune):
+    """Rows of 0-3 elements: a tile holds hundreds of rows, with empty rows
+    between them."""
+    shape = np.random.default_rng(77).integers(0, 4, 200_000).astype(np.int64)
+    keys = W.int_keys(int(shape.sum()), 78)
+    run_both(keys, shape, tune=tune)
+
+
+@pytest.mark.parametrize("tune", [(256, 2), (512, 2), (512, 4), (1024, 4)])
+def test_rows_on_tile_boundaries(tune):
+    """Row starts and ends exactly on tile boundaries (tiles of 2048 to 16384
+    elements), rows filling whole tiles, and empty rows at a boundary."""
+    shape = np.array([4096, 8192, 2048, 2048, 4096 * 3, 1, 4095, 0, 4096, 0, 0, 16384, 2048, 0],
+                     dtype=np.int64)
+    keys = W.int_keys(int(shape.sum()), 79)
+    run_both(keys, shape, tune=tune)
+    run_both(keys, shape, tune=tune, kind="flags",
+             flags=(W.int_keys(int(shape.sum()), 80) % 3 == 0).astype(np.uint8))
+
+
+def test_rows_of_millions_of_elements_among_small_rows():
+    """Rows spanning hundreds of tiles next to rows of a few elements."""
+    shape = np.array([5, 3_000_001, 7, 0, 70_000, 2_500_000, 1], dtype=np.int64)
+    keys = W.int_keys(int(shape.sum()), 81)
+    run_both(keys, shape)
+    run_both(keys, shape, tune=(1024, 4))
+    run_both(keys, shape, mode=1)
