@@ -109,9 +109,10 @@ int ixp_partition(const void *keys, int32_t key_t, int64_t n,
 
 /* Tile shape of the segmented kernels: `block` threads (256, 512 or 1024)
  * each holding `rows` x 4 elements (rows in {2,4,8}, tile <= 16384); a tile
- * is block*rows*4 elements.  `wgs_per_cu` (1..64, 0 = as many as fit) sizes
- * the grid of the main kernel, whose workgroups pull work items from an atomic
- * queue until it is empty.  A NULL tuning pointer selects the default. */
+ * is block*rows*4 elements, and every row is cut into work items of at most
+ * one tile.  `wgs_per_cu` (1..64, 0 = as many as fit) sizes the grid of the
+ * main kernel: workgroup w takes items w, w + grid, w + 2*grid, ...  A NULL
+ * tuning pointer selects the default (512 x 4, as many as fit). */
 typedef struct {
     int32_t block;
     int32_t rows;
@@ -135,7 +136,11 @@ size_t ixp_segmented_workspace(int64_t n, int64_t m, const ixp_tuning *tune);
  *              applied to a row of ones, Section 2.1).
  * A negative size or a size sum different from n is detected on the device:
  * the call then writes no output and ixp_read_error() on the same workspace
- * reports IXP_EINVAL.  One persistent kernel does all rows; 3 kernels total. */
+ * reports IXP_EINVAL.  Enqueues 6 kernels (shape scan, item records, counts
+ * of rows spanning several items, item scan, item bases, main), all
+ * stream-ordered with no host synchronisation: capturable into a HIP graph.
+ * Alignment (else IXP_EINVAL): keys and ws 16 bytes, out_idx 4 indices,
+ * out_keys, d_flags_out and a flag predicate's array 4 bytes. */
 int ixp_segmented_partition(const void *keys, int32_t key_t, int64_t n,
                             const int64_t *d_shape, int64_t m,
                             const ixp_pred *pred, int32_t mode, void *out_keys,
