@@ -44,6 +44,8 @@ def _load():
             "ixo_map_pred": [P, i32, i64, i32, i64, i64, f32, P, P],
             "ixo_scatter": [P, i64, P, P, i64, i64],
             "ixo_gather": [P, P, i64, P, i64, i64],
+            "ixo_hist_min": [P, i64, i64, P, P, i64],
+            "ixo_scatter_checked": [P, i64, P, P, i64, i64, P],
             "ixo_partition2": [P, i32, i64, i32, i64, i64, f32, P, i32, P, P, P],
             "ixo_sgm_sum": [P, P, i64, P],
             "ixo_mk_sgm_descr": [P, i64, P, P, i64],
@@ -198,6 +200,28 @@ def gather(src: np.ndarray, idx: np.ndarray) -> np.ndarray:
     _check(_load().ixo_gather(_ptr(out), _ptr(src), src.shape[0], _ptr(idx),
                               len(idx), row), "gather")
     return out
+
+
+def hist_min(n_dst: int, neutral: int, idx: np.ndarray, vals: Optional[np.ndarray] = None) -> np.ndarray:
+    """Reduce-by-index with min into replicate n_dst neutral (vals None = iota)."""
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    v = None if vals is None else np.ascontiguousarray(vals, dtype=np.int64)
+    out = np.zeros(n_dst, dtype=np.int64)
+    _check(_load().ixo_hist_min(_ptr(out), n_dst, int(neutral), _ptr(idx), _ptr(v), len(idx)),
+           "hist_min")
+    return out
+
+
+def scatter_checked(n_dst: int, idx: np.ndarray, vals: np.ndarray):
+    """Dynamically verified scatter into replicate n_dst 0: (dst, verdict)."""
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    vals = np.ascontiguousarray(vals)
+    dst = np.zeros((n_dst,) + vals.shape[1:], dtype=vals.dtype)
+    row = vals.itemsize * (int(np.prod(vals.shape[1:])) if vals.ndim > 1 else 1)
+    v = np.zeros(3, dtype=np.int64)
+    _check(_load().ixo_scatter_checked(_ptr(dst), n_dst, _ptr(idx), _ptr(vals), len(idx), row,
+                                       _ptr(v)), "scatter_checked")
+    return dst, _verdict(v)
 
 
 def _verdict(v):

@@ -117,6 +117,64 @@ int ixo_gather(void *dst, const void *src, int64_t n_src, const int64_t *is,
     return 0;
 }
 
+/* Reduce-by-index with min (Futhark's `hist i64.min`, used by
+ * get_smallest_pairs in Section 6 and, for the dynamic verification of
+ * scatter, in the evaluation of Section 6):
+ *   dst = replicate n_dst neutral
+ *   for i in 0..m-1: if 0 <= is[i] < n_dst then
+ *       dst[is[i]] := min dst[is[i]] vs[i]
+ * vs == NULL stands for iota m (vs[i] = i). */
+int ixo_hist_min(int64_t *dst, int64_t n_dst, int64_t neutral, const int64_t *is,
+                 const int64_t *vs, int64_t m) {
+    if (n_dst < 0 || m < 0 || (n_dst > 0 && !dst) || (m > 0 && !is)) return -1;
+    for (int64_t v = 0; v < n_dst; v++) dst[v] = neutral;
+    for (int64_t i = 0; i < m; i++) {
+        if (0 <= is[i] && is[i] < n_dst) {
+            int64_t x = vs ? vs[i] : i;
+            if (x < dst[is[i]]) dst[is[i]] = x;
+        }
+    }
+    return 0;
+}
+
+/* Dynamically verified scatter: the "Base" variant of the scatter in
+ * partition2 in the evaluation of Section 6 (table "tab:eval", right),
+ * which checks at run time that no location is written twice, with a
+ * reduce-by-index of atomic minima.  Steps:
+ *   dst = replicate n_dst 0
+ *   win = hist min m (is) (iota m)       -- least i writing each location
+ *   a write i is safe iff is[i] is out of bounds or win[is[i]] == i
+ *   verdict: holds iff every write is safe; first_violation = the least
+ *            unsafe i (the earliest second write to a location), aux = is[i]
+ *   dst[v] = vs[win[v]] for every written location v (the least writer wins).
+ * With an injective `is` this equals scatter (replicate n_dst 0) is vs. */
+int ixo_scatter_checked(void *dst, int64_t n_dst, const int64_t *is, const void *vs,
+                        int64_t m, int64_t elem_bytes, int64_t *verdict) {
+    if (n_dst < 0 || m < 0 || elem_bytes <= 0 || !verdict) return -1;
+    if (m > 0 && (!is || !vs)) return -1;
+    memset(dst, 0, (size_t)(n_dst * elem_bytes));
+    int64_t *win = (int64_t *)malloc((size_t)(n_dst > 0 ? n_dst : 1) * sizeof(int64_t));
+    if (!win) return -2;
+    ixo_hist_min(win, n_dst, m, is, NULL, m);
+    verdict[0] = 1;
+    verdict[1] = -1;
+    verdict[2] = 0;
+    for (int64_t i = 0; i < m; i++) {
+        if (0 <= is[i] && is[i] < n_dst && win[is[i]] != i) {
+            verdict[0] = 0;
+            verdict[1] = i;
+            verdict[2] = is[i];
+            break;
+        }
+    }
+    for (int64_t v = 0; v < n_dst; v++)
+        if (win[v] < m)
+            memcpy((char *)dst + v * elem_bytes, (const char *)vs + win[v] * elem_bytes,
+                   (size_t)elem_bytes);
+    free(win);
+    return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* partition2 (Section 2.1, figure "Running Examples", left):               */
 /*   cs       = map p xs                                                    */

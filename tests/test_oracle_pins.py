@@ -343,3 +343,68 @@ def test_filtpart_holds_on_outputs_and_planted_faults():
     z[drop] = 0
     v = O.check_filtpart(keys, p, O.MODE_FILTER, fy, z, ft)
     assert v[0] == 0 and v[2] & 2
+
+
+# ------------------------------------------- reduce-by-index, checked scatter ---
+
+def test_hist_min_matches_numpy_minimum_at():
+    """hist min against numpy's unbuffered reduce-by-index (ufunc.at), with
+    out-of-bounds and negative indices dropped as the definition says."""
+    g = np.random.default_rng(90)
+    for n_dst, m in [(0, 5), (1, 0), (7, 40), (1000, 5000), (5000, 1000)]:
+        idx = g.integers(-3, n_dst + 3, m)
+        vals = g.integers(-10**12, 10**12, m)
+        neutral = 2**62
+        ref = np.full(n_dst, neutral, dtype=np.int64)
+        keep = (idx >= 0) & (idx < n_dst)
+        np.minimum.at(ref, idx[keep], vals[keep])
+        assert np.array_equal(O.hist_min(n_dst, neutral, idx, vals), ref)
+        # iota values: the least writer of each location
+        ref = np.full(n_dst, m, dtype=np.int64)
+        np.minimum.at(ref, idx[keep], np.arange(m)[keep])
+        assert np.array_equal(O.hist_min(n_dst, m, idx), ref)
+
+
+def test_scatter_checked_injective_equals_scatter():
+    """With injective indices the verified scatter is the plain scatter into
+    zeros and the verdict holds; out-of-bounds writes are dropped."""
+    g = np.random.default_rng(91)
+    n = 10_000
+    idx = g.permutation(n)
+    idx[::37] = -1
+    idx[5::41] = n + 2
+    vals = W.f32_normal(n, 92)
+    dst, v = O.scatter_checked(n, idx, vals)
+    assert v == (1, -1, 0)
+    assert np.array_equal(dst.view(np.uint32), O.scatter(np.zeros(n, np.float32), idx, vals).view(np.uint32))
+
+
+def test_scatter_checked_planted_repeats():
+    """A repeated location: the verdict fails at the planted second write,
+    agrees with the Inj checker over [0, n), and the least writer's value is
+    the one stored."""
+    g = np.random.default_rng(93)
+    n = 5_000
+    idx = g.permutation(n)
+    p, s = 4_000, 1_234          # position p copies the index of s < p
+    idx[p] = idx[s]
+    vals = np.arange(n, dtype=np.int64) * 3 + 1
+    dst, v = O.scatter_checked(n, idx, vals)
+    assert v == (0, p, int(idx[s]))
+    assert v == O.check_inj(idx, 0, n)
+    assert dst[idx[s]] == vals[s]
+    # the location that lost its writer stays zero
+    lost = int(np.setdiff1d(np.arange(n), idx)[0])
+    assert dst[lost] == 0
+    # brute force on a tiny case: every location gets the least writer
+    for trial in range(50):
+        m = int(g.integers(0, 12))
+        k = int(g.integers(1, 8))
+        idx = g.integers(-1, k + 1, m)
+        vals = g.integers(1, 100, m)
+        dst, v = O.scatter_checked(k, idx, vals)
+        for loc in range(k):
+            writers = [i for i in range(m) if idx[i] == loc]
+            assert dst[loc] == (vals[min(writers)] if writers else 0)
+        bad = [i for i in range(m) if 0 <= idx[i] < k and any(idx[j] == idx[i] for j in range(i))]
+        assert v == ((0, bad[0], int(idx[bad[0]])) if bad else (1, -1, 0))
