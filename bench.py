@@ -84,7 +84,7 @@ def main():
     ap.add_argument("--with-copy", action="store_true",
                     help="also run one plain device copy of the input (counter calibration)")
     ap.add_argument("--section", default=None,
-                    help="run only this section (segmented, autograd, props, flat_extra) and print it")
+                    help="run only this section (segmented, autograd, props, verify) and print it")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -101,7 +101,7 @@ def main():
     dev = torch.device("cuda:0")
     if args.section:
         fn = {"segmented": section_segmented, "autograd": section_autograd,
-              "props": section_props}[args.section]
+              "props": section_props, "verify": section_verify}[args.section]
         print(json.dumps({args.section: fn(args, torch, np, P, W, dev)}))
         return
     n = W.FLAT_LARGE_N
@@ -215,6 +215,7 @@ def sections(args, torch, np, P, W, dev, x, out_keys, out_idx, split):
     res["segmented_10^4_rows"] = section_segmented(args, torch, np, P, W, dev)
     res["fwd_bwd_2^24x16"] = section_autograd(args, torch, np, P, W, dev)
     res["check_props_2^28_int64"] = section_props(args, torch, np, P, W, dev)
+    res["scatter_verification_partition2"] = section_verify(args, torch, np, P, W, dev)
     return res
 
 
@@ -349,6 +350,70 @@ def section_props(args, torch, np, P, W, dev):
     out["sorted_mono"] = {"ms": t * 1e3, "GElem_s": n / t / 1e9, "alg_GBps": 8 * n / t / 1e9,
                           "verdicts": P.verdicts(P.check_props(srt, P.MONO))[1:2]}
     return out
+
+
+# The paper's A100 times of partition2 (Section 6, table "tab:eval" right),
+# milliseconds: other hardware, context only.
+PAPER_A100_MS = {50_000_000: {"base": 12.357, "static": 2.814, "static_opt": 2.614},
+                 100_000_000: {"base": 38.947, "static": 5.565, "static_opt": 5.145},
+                 200_000_000: {"base": 135.742, "static": 11.097, "static_opt": 10.557}}
+
+
+def section_verify(args, torch, np, P, W, dev):
+    """partition2 of N random f32 (x < 0.5) with its scatter verified three
+    ways: Base = the indices are materialised, then a dynamically checked
+    scatter (zeroed output, reduce-by-index of atomic minima, check, winner
+    writes); Static = zeroed output, then the fused partition that scatters
+    without checks; Static+Opt = the fused partition alone (the output is not
+    initialised: the index array is a bijection)."""
+    res = {}
+    steps = max(3, args.steps // 4)
+    pred = P.Pred.lt(W.VERIFY_S)
+    for n in W.VERIFY_NS:
+        x = torch.from_numpy(W.f32_uniform(n, W.VERIFY_SEED)).to(dev)
+        dst = torch.empty_like(x)
+        idx = torch.empty(n, dtype=torch.int32, device=dev)
+        split = torch.empty(1, dtype=torch.int64, device=dev)
+        verdict = torch.empty(3, dtype=torch.int64, device=dev)
+
+        def static_opt():
+            P.partition(x, pred, P.MODE_PARTITION, torch.int32, out_keys=dst, want_idx=False, split=split)
+
+        def static():
+            P.zero_(dst)
+            static_opt()
+
+        def base():
+            P.partition(x, pred, P.MODE_PARTITION, torch.int32, want_keys=False, out_idx=idx, split=split)
+            P.scatter_checked(n, idx, x, out=dst, verdict=verdict)
+
+        base()
+        torch.cuda.synchronize()
+        ref = dst.clone()
+        assert int(verdict[0].item()) == 1, "partition indices must verify as injective"
+        r = {}
+        for name, fn in (("base", base), ("static", static), ("static_opt", static_opt)):
+            fn()
+            torch.cuda.synchronize()
+            assert torch.equal(dst, ref), f"{name} differs from the checked scatter"
+            t = timed(fn, steps, 1, torch)
+            r[name] = {"ms": t * 1e3, "GElem_s": n / t / 1e9}
+        r["speedup_static"] = r["base"]["ms"] / r["static"]["ms"]
+        r["speedup_static_opt"] = r["base"]["ms"] / r["static_opt"]["ms"]
+        r["paper_a100_ms"] = PAPER_A100_MS[n]
+        res[f"{n // 1_000_000}M"] = r
+        del x, dst, idx, ref
+    P.profile_enable(True)
+    n = W.VERIFY_NS[-1]
+    x = torch.from_numpy(W.f32_uniform(n, W.VERIFY_SEED)).to(dev)
+    dst = torch.empty_like(x)
+    idx = torch.empty(n, dtype=torch.int32, device=dev)
+    P.partition(x, pred, P.MODE_PARTITION, torch.int32, want_keys=False, out_idx=idx)
+    P.scatter_checked(n, idx, x, out=dst)
+    torch.cuda.synchronize()
+    P.profile_enable(False)
+    res["base_kernels_200M"] = _prof(P)
+    return res
 
 
 def cpu_baseline(W, np):

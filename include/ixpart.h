@@ -14,7 +14,10 @@
  *   - scatter (Section 2.1) restricted to injective index arrays, and its
  *     inverse, a gather;
  *   - run-time checkers of the array properties Range, Monotonic, Inj, Bij and
- *     FiltPart (Section 2.3, figure "Array Properties").
+ *     FiltPart (Section 2.3, figure "Array Properties");
+ *   - the dynamically verified scatter and the reduce-by-index with min that
+ *     the evaluation compares the statically verified path against
+ *     (Section 6).
  *
  * Conventions common to every entry point
  *   - Pointers named d_* or documented as "device" are device pointers
@@ -262,6 +265,40 @@ size_t ixp_check_props_workspace(int64_t n, uint32_t mask,
 int ixp_check_props(const void *x, int32_t x_t, int64_t n, uint32_t mask,
                     const ixp_prop_args *a, ixp_verdict *d_out, void *ws,
                     size_t ws_bytes, void *stream);
+
+/* ---- dynamic verification of scatter, reduce-by-index (Section 6) --------- */
+
+/* Reduce-by-index with min (the `hist i64.min` of get_smallest_pairs,
+ * Section 6): d_dst[0..n_dst) := neutral, then for every i < m with
+ * 0 <= idx[i] < n_dst, d_dst[idx[i]] := min(d_dst[idx[i]], vals[i]); a NULL
+ * `vals` stands for vals[i] = i.  Other indices are ignored.  Device int64
+ * arrays (vals nullable), idx of type idx_t.  Deterministic (min is
+ * order-independent); device atomics, 2 kernels. */
+int ixp_hist_min(int64_t *d_dst, int64_t n_dst, int64_t neutral,
+                 const void *idx, int32_t idx_t, const int64_t *vals,
+                 int64_t m, void *stream);
+
+size_t ixp_scatter_checked_workspace(int64_t n_dst);
+
+/* The dynamically verified scatter of the evaluation's Base variant
+ * (Section 6, table "tab:eval": scatter into a zeroed array, checked at run
+ * time with a reduce-by-index of atomic minima):
+ *   dst[0..n_dst) := 0 (elements of elem_bytes = 4 or 8 bytes);
+ *   win[v] := the least i with idx[i] == v (ixp_hist_min over iota);
+ *   dst[v] := vals[win[v]] for every written location v;
+ *   *d_out  := Inj of idx over [0, n_dst): holds iff no in-bounds location is
+ *             written twice; first_violation = the least i whose location an
+ *             earlier i also writes, aux = idx[first_violation].
+ * Out-of-bounds indices are ignored.  Workspace: ixp_scatter_checked_workspace
+ * bytes, 256-byte aligned (8 bytes per location).  4 kernels. */
+int ixp_scatter_checked(void *dst, int64_t n_dst, const void *idx,
+                        int32_t idx_t, const void *vals, int64_t m,
+                        int64_t elem_bytes, ixp_verdict *d_out, void *ws,
+                        size_t ws_bytes, void *stream);
+
+/* d[0..bytes) := 0 with a kernel (no hipMemset, so it may be captured into
+ * a HIP graph): the initialisation `replicate n 0` of a scattered array. */
+int ixp_zero(void *d, size_t bytes, void *stream);
 
 /* ---- kernel timing ------------------------------------------------------------ */
 /* While enabled, every kernel the library enqueues (outside HIP-graph capture)

@@ -349,6 +349,59 @@ def gather(src: torch.Tensor, idx: torch.Tensor, err: Optional[torch.Tensor] = N
     return out
 
 
+def hist_min(n_dst: int, neutral: int, idx: torch.Tensor, vals: Optional[torch.Tensor] = None,
+             out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Reduce-by-index with min: replicate n_dst neutral, then
+    out[idx[i]] = min(out[idx[i]], vals[i]) (vals None: i); out-of-range
+    indices are ignored.  int64 result."""
+    _check_dev(idx)
+    idx = idx.contiguous()
+    if vals is not None:
+        _check_dev(vals)
+        vals = vals.contiguous()
+        if vals.dtype != torch.int64 or vals.shape[0] != idx.shape[0]:
+            raise ValueError("vals must be int64 with one entry per index")
+    if out is None:
+        out = torch.empty(n_dst, dtype=torch.int64, device=idx.device)
+    rc = L.lib().ixp_hist_min(_ptr(out), n_dst, int(neutral), _ptr(idx), _IDX_T[idx.dtype], _ptr(vals),
+                              idx.shape[0], _stream_ptr(idx.device))
+    L.check(rc, "ixp_hist_min")
+    return out
+
+
+def scatter_checked(n_dst: int, idx: torch.Tensor, vals: torch.Tensor,
+                    out: Optional[torch.Tensor] = None, verdict: Optional[torch.Tensor] = None):
+    """Dynamically verified scatter into a zeroed array of n_dst elements:
+    returns (dst, verdict) with verdict = int64 [holds, first_violation, aux]
+    of Inj over [0, n_dst); where a location is written twice the least
+    index wins."""
+    _check_dev(idx, vals)
+    idx = idx.contiguous()
+    vals = vals.contiguous()
+    if vals.dim() != 1 or vals.element_size() not in (4, 8):
+        raise ValueError("vals must be 1-D with 4- or 8-byte elements")
+    if out is None:
+        out = torch.empty(n_dst, dtype=vals.dtype, device=vals.device)
+    if verdict is None:
+        verdict = torch.empty(3, dtype=torch.int64, device=vals.device)
+    ws = workspace(L.lib().ixp_scatter_checked_workspace(n_dst), vals.device, "checked")
+    rc = L.lib().ixp_scatter_checked(_ptr(out), n_dst, _ptr(idx), _IDX_T[idx.dtype], _ptr(vals),
+                                     idx.shape[0], vals.element_size(), _ptr(verdict), _ptr(ws),
+                                     ws.numel(), _stream_ptr(vals.device))
+    L.check(rc, "ixp_scatter_checked")
+    return out, verdict
+
+
+def zero_(t: torch.Tensor) -> torch.Tensor:
+    """Zeroes a contiguous tensor with the library's fill kernel."""
+    _check_dev(t)
+    if not t.is_contiguous():
+        raise ValueError("zero_ needs a contiguous tensor")
+    rc = L.lib().ixp_zero(_ptr(t), t.numel() * t.element_size(), _stream_ptr(t.device))
+    L.check(rc, "ixp_zero")
+    return t
+
+
 class PartitionScatter(torch.autograd.Function):
     """Differentiable partition of a payload carried by its keys.
 

@@ -23,6 +23,9 @@ SEG_KEYS_SEED = 30
 AUTOGRAD_N = 1 << 24            # int32 keys, payload f32 [n, 16] ~ N(0, 1)
 AUTOGRAD_ROW = 16
 AUTOGRAD_SEEDS = (40, 41, 42)   # keys, payload, upstream gradient
+VERIFY_NS = (50_000_000, 100_000_000, 200_000_000)   # f32 uniform in [0, 1), x < 0.5
+VERIFY_SEED = 20
+VERIFY_S = 0.5
 PROPS_N = 1 << 28               # int64 index arrays
 PROPS_PERM_SEED = 50
 PROPS_SORTED_SEED = 51
