@@ -46,6 +46,7 @@ def _load():
             "ixo_gather": [P, P, i64, P, i64, i64],
             "ixo_hist_min": [P, i64, i64, P, P, i64],
             "ixo_scatter_checked": [P, i64, P, P, i64, i64, P],
+            "ixo_get_smallest_pairs": [i64, i64, P, P, i64, P, P, P],
             "ixo_partition2": [P, i32, i64, i32, i64, i64, f32, P, i32, P, P, P],
             "ixo_sgm_sum": [P, P, i64, P],
             "ixo_mk_sgm_descr": [P, i64, P, P, i64],
@@ -222,6 +223,18 @@ def scatter_checked(n_dst: int, idx: np.ndarray, vals: np.ndarray):
     _check(_load().ixo_scatter_checked(_ptr(dst), n_dst, _ptr(idx), _ptr(vals), len(idx), row,
                                        _ptr(v)), "scatter_checked")
     return dst, _verdict(v)
+
+
+def get_smallest_pairs(n_verts: int, n_es: int, es: np.ndarray, is_: np.ndarray):
+    """(es', is'): the entries holding the least id at their endpoint."""
+    es = np.ascontiguousarray(es, dtype=np.int64)
+    is_ = np.ascontiguousarray(is_, dtype=np.int64)
+    eo = np.zeros(len(es), dtype=np.int64)
+    io = np.zeros(len(es), dtype=np.int64)
+    c = np.zeros(1, dtype=np.int64)
+    _check(_load().ixo_get_smallest_pairs(n_verts, n_es, _ptr(es), _ptr(is_), len(es), _ptr(eo),
+                                          _ptr(io), _ptr(c)), "get_smallest_pairs")
+    return eo[: int(c[0])], io[: int(c[0])]
 
 
 def _verdict(v):

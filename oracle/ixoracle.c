@@ -137,6 +137,35 @@ int ixo_hist_min(int64_t *dst, int64_t n_dst, int64_t neutral, const int64_t *is
     return 0;
 }
 
+/* get_smallest_pairs (Section 6, maximal matching): given edge endpoints es
+ * (Range es [0, n_verts) is a precondition) and injective edge ids `is`, keep
+ * the entries whose id is the least id at their endpoint:
+ *   H  = hist min (neutral n_es) over es with values is      [n_verts]
+ *   cs = for each k: H[es[k]] == is[k]
+ *   es' = filter cs es ; is' = filter cs is   (input order kept)
+ * Entries with es[k] outside [0, n_verts) are not kept (reading: the
+ * precondition makes them absent; here they are dropped).  Writes es', is'
+ * (capacity m each) and their length to *count. */
+int ixo_get_smallest_pairs(int64_t n_verts, int64_t n_es, const int64_t *es, const int64_t *is,
+                           int64_t m, int64_t *es_out, int64_t *is_out, int64_t *count) {
+    if (n_verts < 0 || m < 0 || !count || (m > 0 && (!es || !is || !es_out || !is_out))) return -1;
+    int64_t *H = (int64_t *)malloc((size_t)(n_verts > 0 ? n_verts : 1) * sizeof(int64_t));
+    if (!H) return -2;
+    ixo_hist_min(H, n_verts, n_es, es, is, m);
+    int64_t c = 0;
+    for (int64_t k = 0; k < m; k++) {
+        int keep = 0 <= es[k] && es[k] < n_verts && H[es[k]] == is[k];
+        if (keep) {
+            es_out[c] = es[k];
+            is_out[c] = is[k];
+            c++;
+        }
+    }
+    *count = c;
+    free(H);
+    return 0;
+}
+
 /* Dynamically verified scatter: the "Base" variant of the scatter in
  * partition2 in the evaluation of Section 6 (table "tab:eval", right),
  * which checks at run time that no location is written twice, with a

@@ -408,3 +408,24 @@ def test_scatter_checked_planted_repeats():
             assert dst[loc] == (vals[min(writers)] if writers else 0)
         bad = [i for i in range(m) if 0 <= idx[i] < k and any(idx[j] == idx[i] for j in range(i))]
         assert v == ((0, bad[0], int(idx[bad[0]])) if bad else (1, -1, 0))
+
+
+def test_get_smallest_pairs_against_groupby_min():
+    """The kept pairs are, per endpoint, the least edge id (pandas group-by
+    minimum), listed in input order; both outputs are injective."""
+    import pandas as pd
+    g = np.random.default_rng(95)
+    for n_verts, m in [(1, 10), (50, 40), (1000, 20_000), (100_000, 50_000)]:
+        es = g.integers(0, n_verts, m)
+        is_ = g.permutation(4 * m)[:m]            # injective edge ids
+        eo, io = O.get_smallest_pairs(n_verts, 4 * m, es, is_)
+        mins = pd.DataFrame({"e": es, "i": is_}).groupby("e")["i"].min()
+        keep = is_ == mins.reindex(es).to_numpy()
+        assert np.array_equal(eo, es[keep]) and np.array_equal(io, is_[keep])
+        assert len(eo) == len(mins) == len(np.unique(eo))
+        assert O.check_inj(eo, 0, n_verts)[0] == 1 and O.check_inj(io, 0, 4 * m)[0] == 1
+    # endpoints outside [0, n_verts) are never kept; no edges, no pairs
+    eo, io = O.get_smallest_pairs(3, 10, np.array([5, -1, 2]), np.array([0, 1, 2]))
+    assert eo.tolist() == [2] and io.tolist() == [2]
+    eo, io = O.get_smallest_pairs(3, 10, np.zeros(0, np.int64), np.zeros(0, np.int64))
+    assert len(eo) == 0
