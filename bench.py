@@ -84,7 +84,7 @@ def main():
     ap.add_argument("--with-copy", action="store_true",
                     help="also run one plain device copy of the input (counter calibration)")
     ap.add_argument("--section", default=None,
-                    help="run only this section (segmented, autograd, props, verify) and print it")
+                    help="run only this section (segmented, autograd, props, verify, pairs) and print it")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -101,7 +101,7 @@ def main():
     dev = torch.device("cuda:0")
     if args.section:
         fn = {"segmented": section_segmented, "autograd": section_autograd,
-              "props": section_props, "verify": section_verify}[args.section]
+              "props": section_props, "verify": section_verify, "pairs": section_pairs}[args.section]
         print(json.dumps({args.section: fn(args, torch, np, P, W, dev)}))
         return
     n = W.FLAT_LARGE_N
@@ -216,6 +216,7 @@ def sections(args, torch, np, P, W, dev, x, out_keys, out_idx, split):
     res["fwd_bwd_2^24x16"] = section_autograd(args, torch, np, P, W, dev)
     res["check_props_2^28_int64"] = section_props(args, torch, np, P, W, dev)
     res["scatter_verification_partition2"] = section_verify(args, torch, np, P, W, dev)
+    res["get_smallest_pairs"] = section_pairs(args, torch, np, P, W, dev)
     return res
 
 
@@ -414,6 +415,46 @@ def section_verify(args, torch, np, P, W, dev):
     P.profile_enable(False)
     res["base_kernels_200M"] = _prof(P)
     return res
+
+
+def section_pairs(args, torch, np, P, W, dev):
+    """get_smallest_pairs on a random graph of 2^26 entries over 2^24 vertices:
+    hist min, the keep flags, a filter of the flags and two 8-byte scatters,
+    all enqueued without a host synchronisation; then Inj of both outputs
+    with the device checker.  Compared with the same steps in plain torch
+    (scatter_reduce amin, gather, boolean masks)."""
+    n_verts, m = W.PAIRS_VERTS, W.PAIRS_M
+    e, i = W.graph_entries(n_verts, m, W.PAIRS_SEEDS)
+    es = torch.from_numpy(e).to(dev)
+    is_ = torch.from_numpy(i).to(dev)
+    sp = P.SmallestPairs(n_verts, m, es, is_)
+    steps = max(3, args.steps // 2)
+    t = timed(sp.run, steps, 2, torch)
+    kept = int(sp.split.item())
+    eo, io = sp.es_out[:kept], sp.is_out[:kept]
+
+    def check():
+        return (P.check_props(eo, P.INJ, lo=0, hi=n_verts), P.check_props(io, P.INJ, lo=0, hi=m))
+
+    t_check = timed(check, steps, 1, torch)
+    v1, v2 = (P.verdicts(v)[2] for v in check())
+
+    def torch_ref():
+        h = torch.full((n_verts,), m, dtype=torch.int64, device=dev)
+        h.scatter_reduce_(0, es, is_, reduce="amin", include_self=True)
+        keep = h[es] == is_
+        return es[keep], is_[keep]
+
+    re, ri = torch_ref()
+    assert torch.equal(re, eo) and torch.equal(ri, io), "torch reference disagrees"
+    t_torch = timed(torch_ref, steps, 1, torch)
+    P.profile_enable(True)
+    sp.run()
+    torch.cuda.synchronize()
+    P.profile_enable(False)
+    return {"n_verts": n_verts, "entries": m, "kept": kept, "ms": t * 1e3, "G_entries_s": m / t / 1e9,
+            "inj_check_ms": t_check * 1e3, "inj_es_out": v1, "inj_is_out": v2,
+            "torch_ms": t_torch * 1e3, "speedup_vs_torch": t_torch / t, "kernels": _prof(P)}
 
 
 def cpu_baseline(W, np):

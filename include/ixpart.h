@@ -68,7 +68,8 @@ enum { IXP_I32 = 0, IXP_I64 = 1, IXP_F32 = 2, IXP_U8 = 3 };
  *   IXP_PRED_LT:     keys F32; p(x) = (x < s), one IEEE single comparison,
  *                    NaN gives false.
  *   IXP_PRED_FLAGS:  keys I32 or F32 (moved as bits); p(i) = flags[i] != 0,
- *                    `flags` a device u8 array of length n (partition2L's csL). */
+ *                    `flags` a device u8 array of length n (partition2L's csL;
+ *                    NULL allowed when n == 0). */
 enum { IXP_PRED_MOD_EQ = 0, IXP_PRED_LT = 1, IXP_PRED_FLAGS = 2 };
 typedef struct {
     int32_t kind;
@@ -277,6 +278,15 @@ int ixp_check_props(const void *x, int32_t x_t, int64_t n, uint32_t mask,
 int ixp_hist_min(int64_t *d_dst, int64_t n_dst, int64_t neutral,
                  const void *idx, int32_t idx_t, const int64_t *vals,
                  int64_t m, void *stream);
+
+/* d_flags[k] := 1 if 0 <= idx[k] < n_hist and d_hist[idx[k]] == vals[k],
+ * else 0, for k < m: the `map2 (\i j -> H[i] == j) es is` step of
+ * get_smallest_pairs (Section 6), H being an ixp_hist_min result.  The flags
+ * feed a filter with IXP_PRED_FLAGS.  d_flags 4-byte aligned; int64 hist and
+ * vals; idx of type idx_t.  1 kernel. */
+int ixp_match_min(uint8_t *d_flags, const int64_t *d_hist, int64_t n_hist,
+                  const void *idx, int32_t idx_t, const int64_t *vals,
+                  int64_t m, void *stream);
 
 size_t ixp_scatter_checked_workspace(int64_t n_dst);
 

@@ -78,6 +78,7 @@ SIGNATURES = {
     "ixp_check_props_workspace": (_SZ, [_I64, _U32, _PA]),
     "ixp_check_props": (ctypes.c_int, [_P, _I32, _I64, _U32, _PA, _P, _P, _SZ, _P]),
     "ixp_hist_min": (ctypes.c_int, [_P, _I64, _I64, _P, _I32, _P, _I64, _P]),
+    "ixp_match_min": (ctypes.c_int, [_P, _P, _I64, _P, _I32, _P, _I64, _P]),
     "ixp_scatter_checked_workspace": (_SZ, [_I64]),
     "ixp_scatter_checked": (ctypes.c_int, [_P, _I64, _P, _I32, _P, _I64, _I64, _P, _P, _SZ, _P]),
     "ixp_zero": (ctypes.c_int, [_P, _SZ, _P]),

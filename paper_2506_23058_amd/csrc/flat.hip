@@ -352,7 +352,7 @@ extern "C" int ixp_partition(const void *keys, int32_t key_t, int64_t n, const i
     if (idx_t == IXP_I32 && n > 0x7FFFFFFFll) return IXP_EINVAL;
     if (key_t != IXP_I32 && key_t != IXP_F32) return key_t == IXP_I64 ? IXP_EUNSUPPORTED : IXP_EINVAL;
     HostPred hp;
-    int rc = check_pred(pred, key_t, &hp);
+    int rc = check_pred(pred, key_t, &hp, n);
     if (rc != IXP_OK) return rc;
     const bool need_keys = hp.kind != IXP_PRED_FLAGS || out_keys != nullptr;
     if (n > 0 && need_keys && !keys) return IXP_EINVAL;

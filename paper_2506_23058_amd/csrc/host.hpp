@@ -33,7 +33,8 @@ struct HostPred {
     const uint8_t *flags;
 };
 
-inline int check_pred(const ixp_pred *p, int32_t key_t, HostPred *out) {
+// `n` elements are tested: a flag array may be NULL only when n == 0.
+inline int check_pred(const ixp_pred *p, int32_t key_t, HostPred *out, int64_t n) {
     if (!p) return IXP_EINVAL;
     out->kind = p->kind;
     out->flags = p->flags;
@@ -52,7 +53,7 @@ inline int check_pred(const ixp_pred *p, int32_t key_t, HostPred *out) {
         return key_t == IXP_F32 ? IXP_OK : IXP_EINVAL;
     case IXP_PRED_FLAGS:
         if (key_t != IXP_I32 && key_t != IXP_F32) return IXP_EINVAL;
-        return p->flags ? IXP_OK : IXP_EINVAL;
+        return (p->flags || n == 0) ? IXP_OK : IXP_EINVAL;
     default:
         return IXP_EINVAL;
     }

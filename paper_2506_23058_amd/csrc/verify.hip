@@ -62,6 +62,31 @@ __global__ __launch_bounds__(kVBlock) void hist_min_kernel(int64_t *dst, int64_t
     }
 }
 
+// flags[k] = (0 <= idx[k] < n_hist) && hist[idx[k]] == vals[k]: the
+// `map2 (\i j -> H[i] == j) es is` of get_smallest_pairs.  Four entries per
+// thread, their flags leave as one 32-bit store.
+template <class Idx>
+__global__ __launch_bounds__(kVBlock) void match_min_kernel(uint8_t *flags, const int64_t *hist, int64_t n_hist,
+                                                            const Idx *idx, const int64_t *vals, int64_t m) {
+    const int64_t gstride = static_cast<int64_t>(gridDim.x) * kVBlock;
+    const int64_t groups = (m + 3) / 4;
+    for (int64_t g = static_cast<int64_t>(blockIdx.x) * kVBlock + threadIdx.x; g < groups; g += gstride) {
+        uint32_t w = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t k = 4 * g + q;
+            if (k < m) {
+                const int64_t d = static_cast<int64_t>(idx[k]);
+                const bool keep = 0 <= d && d < n_hist && hist[d] == vals[k];
+                w |= static_cast<uint32_t>(keep) << (8 * q);
+            }
+        }
+        if (4 * g + 4 <= m) stream_store(reinterpret_cast<uint32_t *>(flags + 4 * g), w);
+        else
+            for (int q = 0; 4 * g + q < m; ++q) flags[4 * g + q] = static_cast<uint8_t>(w >> (8 * q));
+    }
+}
+
 struct CheckState {
     unsigned long long first;   // least unsafe write, or ~0
 };
@@ -169,6 +194,26 @@ extern "C" int ixp_hist_min(int64_t *d_dst, int64_t n_dst, int64_t neutral, cons
             IXP_LAUNCH("hist_min", hist_min_kernel<int64_t>, dim3(vgrid(m)), dim3(kVBlock), 0, s, d_dst, n_dst,
                        static_cast<const int64_t *>(idx), vals, m);
     }
+    return launch_status();
+}
+
+extern "C" int ixp_match_min(uint8_t *d_flags, const int64_t *d_hist, int64_t n_hist, const void *idx,
+                             int32_t idx_t, const int64_t *vals, int64_t m, void *stream) {
+    if (n_hist < 0 || m < 0 || (m > 0 && (!d_flags || !idx || !vals)) || (n_hist > 0 && !d_hist))
+        return IXP_EINVAL;
+    if (idx_t != IXP_I32 && idx_t != IXP_I64) return IXP_EINVAL;
+    if (!aligned(d_flags, 4) || !aligned(d_hist, 8) || !aligned(vals, 8) ||
+        !aligned(idx, idx_t == IXP_I32 ? 4 : 8))
+        return IXP_EINVAL;
+    if (m == 0) return IXP_OK;
+    hipStream_t s = as_stream(stream);
+    const int grid = vgrid((m + 3) / 4);
+    if (idx_t == IXP_I32)
+        IXP_LAUNCH("match_min", match_min_kernel<int32_t>, dim3(grid), dim3(kVBlock), 0, s, d_flags, d_hist, n_hist,
+                   static_cast<const int32_t *>(idx), vals, m);
+    else
+        IXP_LAUNCH("match_min", match_min_kernel<int64_t>, dim3(grid), dim3(kVBlock), 0, s, d_flags, d_hist, n_hist,
+                   static_cast<const int64_t *>(idx), vals, m);
     return launch_status();
 }
 

@@ -402,6 +402,72 @@ def zero_(t: torch.Tensor) -> torch.Tensor:
     return t
 
 
+def match_min(hist: torch.Tensor, idx: torch.Tensor, vals: torch.Tensor,
+              out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """uint8 flags: hist[idx[k]] == vals[k] for in-range idx[k]."""
+    _check_dev(hist, idx, vals)
+    idx = idx.contiguous()
+    vals = vals.contiguous()
+    m = idx.shape[0]
+    if out is None:
+        out = torch.empty(m, dtype=torch.uint8, device=idx.device)
+    rc = L.lib().ixp_match_min(_ptr(out), _ptr(hist), hist.shape[0], _ptr(idx), _IDX_T[idx.dtype],
+                               _ptr(vals), m, _stream_ptr(idx.device))
+    L.check(rc, "ixp_match_min")
+    return out
+
+
+class SmallestPairs:
+    """get_smallest_pairs (Section 6, maximal matching) on the device, with
+    buffers kept across calls: H = hist min over es with values is, keep
+    entry k iff H[es[k]] == is[k], and filter es and is by the kept flags
+    (positions from a filter over the flags, then two 8-byte scatters).
+    ``run`` enqueues everything without a host synchronisation and leaves the
+    number of kept pairs in ``split``; ``__call__`` returns the trimmed
+    outputs (synchronising)."""
+
+    def __init__(self, n_verts: int, n_es: int, es: torch.Tensor, is_: torch.Tensor):
+        _check_dev(es, is_)
+        if es.dtype != torch.int64 or is_.dtype != torch.int64 or es.shape != is_.shape:
+            raise ValueError("es and is must be int64 arrays of one length")
+        self.n_verts, self.n_es = int(n_verts), int(n_es)
+        self.es, self.is_ = es.contiguous(), is_.contiguous()
+        m = es.shape[0]
+        dev = es.device
+        self.hist = torch.empty(max(self.n_verts, 1), dtype=torch.int64, device=dev)
+        self.flags = torch.empty(m, dtype=torch.uint8, device=dev)
+        self.pos = torch.empty(m, dtype=torch.int64, device=dev)
+        self.es_out = torch.empty(m, dtype=torch.int64, device=dev)
+        self.is_out = torch.empty(m, dtype=torch.int64, device=dev)
+        self.split = torch.empty(1, dtype=torch.int64, device=dev)
+        self.ws = torch.empty(max(L.lib().ixp_partition_workspace(m), 256), dtype=torch.uint8, device=dev)
+        self._pred = Pred.from_flags(self.flags).c()
+
+    def run(self):
+        lib, m, st = L.lib(), self.es.shape[0], _stream_ptr(self.es.device)
+        L.check(lib.ixp_hist_min(_ptr(self.hist), self.n_verts, self.n_es, _ptr(self.es), L.I64,
+                                 _ptr(self.is_), m, st), "ixp_hist_min")
+        L.check(lib.ixp_match_min(_ptr(self.flags), _ptr(self.hist), self.n_verts, _ptr(self.es), L.I64,
+                                  _ptr(self.is_), m, st), "ixp_match_min")
+        L.check(lib.ixp_partition(None, L.I32, m, ctypes.byref(self._pred), L.MODE_FILTER, None,
+                                  _ptr(self.pos), L.I64, _ptr(self.split), _ptr(self.ws), self.ws.numel(), st),
+                "ixp_partition")
+        for src, dst in ((self.es, self.es_out), (self.is_, self.is_out)):
+            L.check(lib.ixp_scatter_inj(_ptr(dst), m, _ptr(self.pos), L.I64, _ptr(src), m, 8, st),
+                    "ixp_scatter_inj")
+        return self.es_out, self.is_out, self.split
+
+    def __call__(self):
+        self.run()
+        c = int(self.split.item())
+        return self.es_out[:c], self.is_out[:c]
+
+
+def get_smallest_pairs(n_verts: int, n_es: int, es: torch.Tensor, is_: torch.Tensor):
+    """(es', is'): the entries whose id is the least id at their endpoint."""
+    return SmallestPairs(n_verts, n_es, es, is_)()
+
+
 class PartitionScatter(torch.autograd.Function):
     """Differentiable partition of a payload carried by its keys.
 

@@ -26,6 +26,9 @@ AUTOGRAD_SEEDS = (40, 41, 42)   # keys, payload, upstream gradient
 VERIFY_NS = (50_000_000, 100_000_000, 200_000_000)   # f32 uniform in [0, 1), x < 0.5
 VERIFY_SEED = 20
 VERIFY_S = 0.5
+PAIRS_VERTS = 1 << 24           # get_smallest_pairs: endpoints uniform in [0, 2^24)
+PAIRS_M = 1 << 26               # entries; ids are a permutation of [0, 2^26)
+PAIRS_SEEDS = (21, 22)          # endpoints, ids
 PROPS_N = 1 << 28               # int64 index arrays
 PROPS_PERM_SEED = 50
 PROPS_SORTED_SEED = 51
@@ -118,3 +121,11 @@ def adjacent_swaps(x: np.ndarray, k: int, seed: int) -> np.ndarray:
             y[i], y[i + 1] = y[i + 1], y[i]
             done += 1
     return y
+
+
+def graph_entries(n_verts: int, m: int, seeds=(21, 22)):
+    """Edge entries of a random graph: endpoints uniform in [0, n_verts)
+    (Poisson degrees) and injective ids, a random permutation of [0, m)."""
+    e = np.random.Generator(np.random.PCG64(seeds[0])).integers(0, n_verts, m, dtype=np.int64)
+    i = np.random.Generator(np.random.PCG64(seeds[1])).permutation(m).astype(np.int64)
+    return e, i
