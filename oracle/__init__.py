@@ -47,6 +47,7 @@ def _load():
             "ixo_hist_min": [P, i64, i64, P, P, i64],
             "ixo_scatter_checked": [P, i64, P, P, i64, i64, P],
             "ixo_get_smallest_pairs": [i64, i64, P, P, i64, P, P, P],
+            "ixo_partition_v": [P, i64, i32, i32, P, P, P, P, P],
             "ixo_partition2": [P, i32, i64, i32, i64, i64, f32, P, i32, P, P, P],
             "ixo_sgm_sum": [P, P, i64, P],
             "ixo_mk_sgm_descr": [P, i64, P, P, i64],
@@ -235,6 +236,25 @@ def get_smallest_pairs(n_verts: int, n_es: int, es: np.ndarray, is_: np.ndarray)
     _check(_load().ixo_get_smallest_pairs(n_verts, n_es, _ptr(es), _ptr(is_), len(es), _ptr(eo),
                                           _ptr(io), _ptr(c)), "get_smallest_pairs")
     return eo[: int(c[0])], io[: int(c[0])]
+
+
+CLASS_MOD, CLASS_THRESH, CLASS_BYTES = 0, 1, 2
+
+
+def partition_v(xs: Optional[np.ndarray], v: int, kind: int, s=(0.0, 0.0, 0.0),
+                cls: Optional[np.ndarray] = None, n: Optional[int] = None):
+    """v-way stable partition: (ys, idx, counts)."""
+    if xs is not None:
+        xs = np.ascontiguousarray(xs)
+        n = len(xs)
+    sv = np.ascontiguousarray(np.array(list(s) + [0.0] * (3 - len(s)), dtype=np.float32))
+    c = None if cls is None else np.ascontiguousarray(cls, dtype=np.uint8)
+    ys = np.zeros(n, dtype=xs.dtype if xs is not None else np.int32)
+    idx = np.zeros(n, dtype=np.int64)
+    counts = np.zeros(4, dtype=np.int64)
+    _check(_load().ixo_partition_v(_ptr(xs), n, kind, v, _ptr(sv), _ptr(c), _ptr(ys), _ptr(idx),
+                                   _ptr(counts)), "partition_v")
+    return ys, idx, counts[:v]
 
 
 def _verdict(v):

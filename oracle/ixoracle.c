@@ -204,6 +204,65 @@ int ixo_scatter_checked(void *dst, int64_t n_dst, const int64_t *is, const void 
     return 0;
 }
 
+/* v-way partition (FiltPart with v pairwise exclusive predicates p_1..p_v,
+ * Section 2.3, figure "Array Properties": with no filtering, the elements
+ * satisfying p_1 come first, then those satisfying p_2, and so on, each class
+ * in input order; partition3 of the evaluation, Section 6, is v = 3).
+ * The class of element i is the h - 1 of its predicate p_h; the last class is
+ * everything no earlier predicate takes (p_v = not (p_1 or ... or p_{v-1})).
+ * Class kinds:
+ *   IXO_CLASS_MOD:    int32 keys, class = floor-mod(key, v);
+ *   IXO_CLASS_THRESH: f32 keys, p_1 = x < s[0], p_h = s[h-2] <= x < s[h-1],
+ *                     with s non-decreasing; NaN takes no p_h, h < v, so it
+ *                     is in the last class;
+ *   IXO_CLASS_BYTES:  class = min(cls[i], v - 1) from a byte array.
+ * Steps: the classes; N_c = number of elements of class c; base_c = N_0 +
+ * ... + N_{c-1}; idx[i] = base_{c(i)} + (number of earlier elements of
+ * class c(i)); ys = scatter zeros idx xs; counts[c] = N_c. */
+enum { IXO_CLASS_MOD = 0, IXO_CLASS_THRESH = 1, IXO_CLASS_BYTES = 2 };
+
+static int class_of(int32_t kind, int32_t v, const float *s, const void *xs, const uint8_t *cls,
+                    int64_t i) {
+    if (kind == IXO_CLASS_MOD) {
+        int64_t x = ((const int32_t *)xs)[i];
+        int64_t r = x % v;
+        return (int)(r < 0 ? r + v : r);
+    }
+    if (kind == IXO_CLASS_THRESH) {
+        float x = ((const float *)xs)[i];
+        for (int h = 0; h < v - 1; h++) {
+            int lower_ok = h == 0 ? 1 : (s[h - 1] <= x);
+            if (lower_ok && x < s[h]) return h;
+        }
+        return v - 1;
+    }
+    return cls[i] < v - 1 ? cls[i] : v - 1;
+}
+
+int ixo_partition_v(const void *xs, int64_t n, int32_t kind, int32_t v, const float *s,
+                    const uint8_t *cls, void *ys, int64_t *idx, int64_t *counts) {
+    if (n < 0 || v < 2 || v > 4 || !counts || (n > 0 && (!ys || !idx))) return -1;
+    if (kind == IXO_CLASS_BYTES ? (n > 0 && !cls) : (n > 0 && !xs)) return -1;
+    if (kind == IXO_CLASS_THRESH)
+        for (int h = 1; h < v - 1; h++)
+            if (!(s[h - 1] <= s[h])) return -1;
+    int *c = (int *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int));
+    if (!c) return -2;
+    for (int h = 0; h < v; h++) counts[h] = 0;
+    for (int64_t i = 0; i < n; i++) {
+        c[i] = class_of(kind, v, s, xs, cls, i);
+        counts[c[i]]++;
+    }
+    int64_t base[4], seen[4] = {0, 0, 0, 0};
+    base[0] = 0;
+    for (int h = 1; h < v; h++) base[h] = base[h - 1] + counts[h - 1];
+    for (int64_t i = 0; i < n; i++) idx[i] = base[c[i]] + seen[c[i]]++;
+    memset(ys, 0, (size_t)(n * 4));
+    ixo_scatter(ys, n, idx, xs ? xs : (const void *)ys, xs ? n : 0, 4);
+    free(c);
+    return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* partition2 (Section 2.1, figure "Running Examples", left):               */
 /*   cs       = map p xs                                                    */

@@ -429,3 +429,57 @@ def test_get_smallest_pairs_against_groupby_min():
     assert eo.tolist() == [2] and io.tolist() == [2]
     eo, io = O.get_smallest_pairs(3, 10, np.zeros(0, np.int64), np.zeros(0, np.int64))
     assert len(eo) == 0
+
+
+# ------------------------------------------------------------ v-way partition ---
+
+def _classes_ref(kind, v, xs=None, s=None, cls=None):
+    if kind == O.CLASS_MOD:
+        return np.mod(xs.astype(np.int64), v)
+    if kind == O.CLASS_THRESH:
+        c = np.full(len(xs), v - 1)
+        for h in reversed(range(v - 1)):
+            lo = -np.inf if h == 0 else s[h - 1]
+            c = np.where((xs >= lo) & (xs < s[h]), h, c)
+        return c
+    return np.minimum(cls, v - 1)
+
+
+def test_partition_v_is_stable_sort_by_class():
+    """The v-way partition is the stable sort by class (numpy argsort with a
+    stable kind, Python's sorted on tiny inputs); counts are bincount."""
+    g = np.random.default_rng(96)
+    for v in (2, 3, 4):
+        for n in (0, 1, 17, 10_000):
+            xs = W.int_keys(n, 97 + n).astype(np.int32) - (1 << 30)
+            xf = g.random(n, dtype=np.float32)
+            xf[::13] = np.nan
+            s = np.sort(g.random(3)).astype(np.float32)
+            cls = g.integers(0, 6, n).astype(np.uint8)
+            for kind, x in ((O.CLASS_MOD, xs), (O.CLASS_THRESH, xf), (O.CLASS_BYTES, xs)):
+                c = _classes_ref(kind, v, x, s, cls)
+                ys, idx, counts = O.partition_v(x, v, kind, tuple(s), cls)
+                order = np.argsort(c, kind="stable")
+                assert np.array_equal(ys.view(np.uint32), x[order].view(np.uint32))
+                inv = np.empty(n, dtype=np.int64)
+                inv[order] = np.arange(n)
+                assert np.array_equal(idx, inv)
+                assert np.array_equal(counts, np.bincount(c, minlength=v)[:v])
+                if n <= 17:
+                    assert list(order) == sorted(range(n), key=lambda i: c[i])
+
+
+def test_partition_v_two_classes_is_partition2():
+    xs = W.int_keys(5000, 98)
+    ys, idx, counts = O.partition_v(xs, 2, O.CLASS_MOD)
+    ys2, idx2, t = O.partition2(xs, O.Pred.mod_eq(2, 0))
+    assert np.array_equal(ys, ys2) and np.array_equal(idx, idx2) and counts[0] == t
+    xf = W.f32_uniform(5000, 99)
+    ys, idx, counts = O.partition_v(xf, 2, O.CLASS_THRESH, (0.3,))
+    ys2, idx2, t = O.partition2(xf, O.Pred.lt(0.3))
+    assert np.array_equal(ys, ys2) and np.array_equal(idx, idx2) and counts[0] == t
+
+
+def test_partition_v_rejects_unsorted_thresholds():
+    with pytest.raises(ValueError):
+        O.partition_v(np.zeros(4, np.float32), 3, O.CLASS_THRESH, (0.5, 0.2))
