@@ -84,7 +84,8 @@ def main():
     ap.add_argument("--with-copy", action="store_true",
                     help="also run one plain device copy of the input (counter calibration)")
     ap.add_argument("--section", default=None,
-                    help="run only this section (segmented, autograd, props, verify, pairs) and print it")
+                    help="run only this section (segmented, autograd, props, verify, pairs, "
+                         "partition3) and print it")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -101,7 +102,8 @@ def main():
     dev = torch.device("cuda:0")
     if args.section:
         fn = {"segmented": section_segmented, "autograd": section_autograd,
-              "props": section_props, "verify": section_verify, "pairs": section_pairs}[args.section]
+              "props": section_props, "verify": section_verify, "pairs": section_pairs,
+              "partition3": section_partition3}[args.section]
         print(json.dumps({args.section: fn(args, torch, np, P, W, dev)}))
         return
     n = W.FLAT_LARGE_N
@@ -217,6 +219,7 @@ def sections(args, torch, np, P, W, dev, x, out_keys, out_idx, split):
     res["check_props_2^28_int64"] = section_props(args, torch, np, P, W, dev)
     res["scatter_verification_partition2"] = section_verify(args, torch, np, P, W, dev)
     res["get_smallest_pairs"] = section_pairs(args, torch, np, P, W, dev)
+    res["partition3_2^28_f32"] = section_partition3(args, torch, np, P, W, dev, x)
     return res
 
 
@@ -455,6 +458,29 @@ def section_pairs(args, torch, np, P, W, dev):
     return {"n_verts": n_verts, "entries": m, "kept": kept, "ms": t * 1e3, "G_entries_s": m / t / 1e9,
             "inj_check_ms": t_check * 1e3, "inj_es_out": v1, "inj_is_out": v2,
             "torch_ms": t_torch * 1e3, "speedup_vs_torch": t_torch / t, "kernels": _prof(P)}
+
+
+def section_partition3(args, torch, np, P, W, dev, x=None):
+    """3-way stable partition of the headline's 2^28 f32 input into
+    x < 1/3, 1/3 <= x < 2/3 and the rest, int32 positions: 12 algorithmic
+    bytes per element (16 with the counting pass), as partition2."""
+    if x is None:
+        x = torch.from_numpy(W.f32_uniform(W.FLAT_LARGE_N, W.FLAT_LARGE_SEED)).to(dev)
+    n = x.numel()
+    ok = torch.empty_like(x)
+    oi = torch.empty(n, dtype=torch.int32, device=dev)
+    cnt = torch.empty(3, dtype=torch.int64, device=dev)
+    cl = P.Classes.thresholds(1 / 3, 2 / 3)
+    steps = max(3, args.steps // 2)
+    t = timed(lambda: P.partition_v(x, cl, torch.int32, out_keys=ok, out_idx=oi, counts=cnt), steps, 2, torch)
+    P.profile_enable(True)
+    P.partition_v(x, cl, torch.int32, out_keys=ok, out_idx=oi, counts=cnt)
+    torch.cuda.synchronize()
+    P.profile_enable(False)
+    k = _prof(P)
+    sc = k.get("flatv_scatter", {}).get("avg_ms", 0.0)
+    return {"ms": t * 1e3, "GElem_s": n / t / 1e9, "counts": cnt.cpu().tolist(),
+            "scatter_alg_GBps": 12 * n / (sc * 1e-3) / 1e9 if sc else None, "kernels": k}
 
 
 def cpu_baseline(W, np):

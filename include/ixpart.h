@@ -8,6 +8,8 @@
  *     partition built from map (the predicate), scan (+) of the flags, an
  *     index map and a scatter;
  *   - filter (FiltPart with a filtering predicate, Section 2.3 and Section 6);
+ *   - the v-way partition (FiltPart with v predicates, Section 2.3;
+ *     partition3 of Section 6);
  *   - partition2L / filter_seg (Section 6, "Segmented operations"): the same
  *     applied to every row of a jagged array given by its shape, rows may be
  *     empty;
@@ -108,6 +110,44 @@ int ixp_partition(const void *keys, int32_t key_t, int64_t n,
                   const ixp_pred *pred, int32_t mode, void *out_keys,
                   void *out_idx, int32_t idx_t, int64_t *d_split, void *ws,
                   size_t ws_bytes, void *stream);
+
+/* ---- v-way partition (partition3) ----------------------------------------- */
+
+/* The class c(i) in [0, v) of element i, 2 <= v <= 4: the v pairwise exclusive
+ * predicates p_1..p_v of FiltPart (Section 2.3), p_{c+1} holding for class c
+ * and p_v = not (p_1 or ... or p_{v-1}).
+ *   IXP_CLASS_MOD:    int32 keys, c = floor-mod(key, v);
+ *   IXP_CLASS_THRESH: f32 keys, thresholds s[0] <= ... <= s[v-2]: class h
+ *                     for s[h-1] <= x < s[h] (class 0: x < s[0]), the last
+ *                     class for x >= s[v-2] and for NaN;
+ *   IXP_CLASS_BYTES:  c = min(classes[i], v - 1), `classes` a device u8[n]
+ *                     (4-byte aligned; NULL allowed when n == 0). */
+enum { IXP_CLASS_MOD = 0, IXP_CLASS_THRESH = 1, IXP_CLASS_BYTES = 2 };
+
+typedef struct {
+    int32_t kind;
+    int32_t v;
+    float s[3];
+    int32_t reserved;
+    const uint8_t *classes;   /* device */
+} ixp_classes;
+
+size_t ixp_partition_v_workspace(int64_t n);
+
+/* Stable v-way partition of keys[0..n) (FiltPart with v predicates and no
+ * filtering, Section 2.3; partition3 of Section 6 is v = 3): class 0 first,
+ * then class 1, ..., each class in input order.
+ *   out_idx[i]   = N_0 + ... + N_{c(i)-1} + #earlier elements of class c(i);
+ *   out_keys     = scatter of the keys by out_idx (length n);
+ *   d_counts[c]  = N_c, the size of class c (device int64[v]).
+ * key_t IXP_I32 or IXP_F32 (moved as bits); idx_t IXP_I32 (n < 2^31) or
+ * IXP_I64.  out_keys / out_idx may be NULL.  Alignment (else IXP_EINVAL): keys
+ * 16 bytes, out_idx 4 indices, out_keys 4 bytes.  Unsorted thresholds are
+ * IXP_EINVAL.  Enqueues 3 kernels; capturable into a HIP graph. */
+int ixp_partition_v(const void *keys, int32_t key_t, int64_t n,
+                    const ixp_classes *cls, void *out_keys, void *out_idx,
+                    int32_t idx_t, int64_t *d_counts, void *ws,
+                    size_t ws_bytes, void *stream);
 
 /* ---- segmented partition (partition2L / filter_seg) ----------------------- */
 

@@ -18,6 +18,7 @@ I32, I64, F32, U8 = 0, 1, 2, 3
 PRED_MOD_EQ, PRED_LT, PRED_FLAGS = 0, 1, 2
 MODE_PARTITION, MODE_FILTER = 0, 1
 RANGE, MONO, INJ, BIJ, FILTPART = 1, 2, 4, 8, 16
+CLASS_MOD, CLASS_THRESH, CLASS_BYTES = 0, 1, 2
 MONO_LE, MONO_LT, MONO_GE, MONO_GT = 0, 1, 2, 3
 
 
@@ -25,6 +26,11 @@ class ixp_pred(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("reserved0", ctypes.c_int32),
                 ("d", ctypes.c_int64), ("r", ctypes.c_int64), ("s", ctypes.c_float),
                 ("reserved1", ctypes.c_int32), ("flags", ctypes.c_void_p)]
+
+
+class ixp_classes(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("v", ctypes.c_int32), ("s", ctypes.c_float * 3),
+                ("reserved", ctypes.c_int32), ("classes", ctypes.c_void_p)]
 
 
 class ixp_tuning(ctypes.Structure):
@@ -56,6 +62,7 @@ _P, _I32, _I64, _U32, _SZ, _F = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
                                  ctypes.c_uint32, ctypes.c_size_t, ctypes.c_float)
 _PP = ctypes.POINTER(ixp_pred)
 _PT = ctypes.POINTER(ixp_tuning)
+_PC = ctypes.POINTER(ixp_classes)
 _PA = ctypes.POINTER(ixp_prop_args)
 SIGNATURES = {
     "ixp_status_str": (ctypes.c_char_p, [ctypes.c_int]),
@@ -63,6 +70,8 @@ SIGNATURES = {
     "ixp_read_error": (ctypes.c_int, [_P, _P]),
     "ixp_partition_workspace": (_SZ, [_I64]),
     "ixp_partition": (ctypes.c_int, [_P, _I32, _I64, _PP, _I32, _P, _P, _I32, _P, _P, _SZ, _P]),
+    "ixp_partition_v_workspace": (_SZ, [_I64]),
+    "ixp_partition_v": (ctypes.c_int, [_P, _I32, _I64, _PC, _P, _P, _I32, _P, _P, _SZ, _P]),
     "ixp_segmented_workspace": (_SZ, [_I64, _I64, _PT]),
     "ixp_segmented_partition": (ctypes.c_int, [_P, _I32, _I64, _P, _I64, _PP, _I32, _P, _P,
                                                _I32, _P, _P, _PT, _P, _SZ, _P]),

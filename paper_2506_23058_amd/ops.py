@@ -110,6 +110,61 @@ def partition(keys: torch.Tensor, pred: Pred, mode: int = L.MODE_PARTITION,
     return (out_keys if want_keys else None), (out_idx if want_idx else None), split
 
 
+class Classes:
+    """Classes of the v-way partition (2 <= v <= 4): floor-mod of an int32
+    key, f32 thresholds s[0] <= s[1] <= ..., or a uint8 class per element."""
+
+    def __init__(self, kind: int, v: int, s=(), classes: Optional[torch.Tensor] = None):
+        self.kind, self.v = int(kind), int(v)
+        self.s = tuple(float(x) for x in s) + (0.0,) * (3 - len(s))
+        self.classes = classes.contiguous() if classes is not None else None
+
+    @staticmethod
+    def mod(v: int) -> "Classes":
+        return Classes(L.CLASS_MOD, v)
+
+    @staticmethod
+    def thresholds(*s: float) -> "Classes":
+        return Classes(L.CLASS_THRESH, len(s) + 1, s)
+
+    @staticmethod
+    def from_bytes(classes: torch.Tensor, v: int) -> "Classes":
+        return Classes(L.CLASS_BYTES, v, classes=classes.to(torch.uint8))
+
+    def c(self) -> L.ixp_classes:
+        c = L.ixp_classes()
+        c.kind, c.v = self.kind, self.v
+        for i in range(3):
+            c.s[i] = self.s[i]
+        c.classes = self.classes.data_ptr() if self.classes is not None else None
+        return c
+
+
+def partition_v(keys: torch.Tensor, classes: Classes, idx_dtype=torch.int64, want_keys: bool = True,
+                want_idx: bool = True, out_keys: Optional[torch.Tensor] = None,
+                out_idx: Optional[torch.Tensor] = None, counts: Optional[torch.Tensor] = None):
+    """Stable v-way partition of a 1-D int32/f32 tensor: (out_keys, out_idx,
+    counts) with counts the int64 class sizes on the device."""
+    _check_dev(keys)
+    keys = keys.contiguous()
+    n = keys.numel()
+    dev = keys.device
+    if want_keys and out_keys is None:
+        out_keys = torch.empty_like(keys)
+    if want_idx and out_idx is None:
+        out_idx = torch.empty(n, dtype=idx_dtype, device=dev)
+    if counts is None:
+        counts = torch.empty(classes.v, dtype=torch.int64, device=dev)
+    ws = workspace(L.lib().ixp_partition_v_workspace(n), dev, "partition_v")
+    cc = classes.c()
+    rc = L.lib().ixp_partition_v(
+        _ptr(keys), _KEY_T[keys.dtype], n, ctypes.byref(cc), _ptr(out_keys) if want_keys else None,
+        _ptr(out_idx) if want_idx else None, _IDX_T[idx_dtype if out_idx is None else out_idx.dtype],
+        _ptr(counts), _ptr(ws), ws.numel(), _stream_ptr(dev))
+    L.check(rc, "ixp_partition_v")
+    return (out_keys if want_keys else None), (out_idx if want_idx else None), counts
+
+
 def read_error(ws: torch.Tensor) -> int:
     """Blocking: the device error recorded in a workspace (0 if none)."""
     return L.lib().ixp_read_error(_ptr(ws), _stream_ptr(ws.device))
