@@ -87,7 +87,7 @@ struct TileV {
     uint32_t key[ROWS][4];
     uint32_t rank[ROWS][4];   // rank among the tile's elements of the same class
     uint32_t c0 = 0, c1 = 0, vbits = 0;
-    uint32_t wtotal[V];
+    uint64_t wtotal = 0;   // packed per-class counts of this wave's run
 
     __device__ static __forceinline__ int64_t pos(int64_t base, int wave, int r, int lane) {
         return base + static_cast<int64_t>(wave) * kPerWave + r * (kWave * 4) + lane * 4;
@@ -162,74 +162,93 @@ struct TileV {
         }
     }
 
-    // Per-class counts of this wave's valid elements (uniform), no ranks.
-    __device__ __forceinline__ void wave_counts(uint32_t (&cnt)[V]) const {
-#pragma unroll
-        for (int k = 0; k < V; ++k) cnt[k] = 0;
+    // One-hot counters packed 16 bits per class in a 64-bit word (a class
+    // holds at most 4096 elements of a tile, so no field overflows).
+    __device__ __forceinline__ uint64_t onehot(int r, int q) const {
+        return valid(r, q) ? (1ull << (16 * cls(r, q))) : 0ull;
+    }
+    __device__ static __forceinline__ uint32_t field(uint64_t x, uint32_t c) {
+        return static_cast<uint32_t>(x >> (16 * c)) & 0xFFFFu;
+    }
+
+    // Per-class counts of this wave's valid elements (uniform), packed.
+    __device__ __forceinline__ uint64_t wave_counts() const {
+        uint64_t x = 0;
 #pragma unroll
         for (int r = 0; r < ROWS; ++r)
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
+            for (int q = 0; q < 4; ++q) x += onehot(r, q);
 #pragma unroll
-                for (int k = 0; k < V; ++k)
-                    cnt[k] += static_cast<uint32_t>(
-                        __builtin_popcountll(ballot(valid(r, q) && cls(r, q) == static_cast<uint32_t>(k))));
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, kWave);
+        return x;
     }
 
-    // Ranks inside this wave's run: one ballot per class and (row, quad).
-    __device__ __forceinline__ void wave_ranks() {
-        uint32_t acc[V];
-#pragma unroll
-        for (int k = 0; k < V; ++k) acc[k] = 0;
+    // Ranks inside this wave's run.  Per row, the counts of every class but
+    // the last are packed 9 bits each into 32 bits (a row of a wave holds at
+    // most 256 elements) and scanned over the lanes with shuffles; the rank
+    // of a last-class element is its position minus the earlier elements of
+    // the other classes (the valid elements of a run form a prefix).
+    __device__ static __forceinline__ uint32_t onehot9(uint32_t c, bool ok) {
+        return (ok && c < static_cast<uint32_t>(V - 1)) ? (1u << (9 * c)) : 0u;
+    }
+    __device__ __forceinline__ void wave_ranks(int lane) {
+        uint64_t acc = 0;   // packed 16-bit counts of the earlier rows (uniform)
 #pragma unroll
         for (int r = 0; r < ROWS; ++r) {
-            uint32_t below[V], tot[V], mine[V];
+            uint32_t mine = 0;
 #pragma unroll
-            for (int k = 0; k < V; ++k) below[k] = tot[k] = mine[k] = 0;
+            for (int q = 0; q < 4; ++q) mine += onehot9(cls(r, q), valid(r, q));
+            uint32_t inc = mine;
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
-#pragma unroll
-                for (int k = 0; k < V; ++k) {
-                    const uint64_t m = ballot(valid(r, q) && cls(r, q) == static_cast<uint32_t>(k));
-                    below[k] += rank_below(m);
-                    tot[k] += static_cast<uint32_t>(__builtin_popcountll(m));
-                }
+            for (int off = 1; off < kWave; off <<= 1) {
+                const uint32_t o = __shfl_up(inc, off, kWave);
+                if (lane >= off) inc += o;
+            }
+            uint32_t run = inc - mine;
+            const uint32_t pos0 = static_cast<uint32_t>(r * kWave * 4 + lane * 4);
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const uint32_t c = cls(r, q);
-                rank[r][q] = pick<V>(acc, c) + pick<V>(below, c) + pick<V>(mine, c);
-                const uint32_t one = valid(r, q) ? 1u : 0u;
+                uint32_t others = 0;   // earlier elements of the classes before the last
 #pragma unroll
-                for (int k = 0; k < V; ++k) mine[k] += c == static_cast<uint32_t>(k) ? one : 0u;
+                for (int k = 0; k < V - 1; ++k) others += field(acc, k) + ((run >> (9 * k)) & 0x1FFu);
+                const uint32_t mine_c = c < static_cast<uint32_t>(V - 1)
+                                            ? field(acc, c) + ((run >> (9 * c)) & 0x1FFu)
+                                            : pos0 + q - others;
+                rank[r][q] = mine_c;
+                run += onehot9(c, valid(r, q));
             }
+            const uint32_t row = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(inc), kWave - 1));
 #pragma unroll
-            for (int k = 0; k < V; ++k) acc[k] += tot[k];
+            for (int k = 0; k < V - 1; ++k) acc += static_cast<uint64_t>((row >> (9 * k)) & 0x1FFu) << (16 * k);
         }
+        // the last class of the run: valid elements minus the others
+        uint32_t nvalid = static_cast<uint32_t>(__builtin_popcount(vbits));
 #pragma unroll
-        for (int k = 0; k < V; ++k) wtotal[k] = acc[k];
+        for (int off = 32; off > 0; off >>= 1) nvalid += __shfl_xor(nvalid, off, kWave);
+        uint32_t others = 0;
+#pragma unroll
+        for (int k = 0; k < V - 1; ++k) others += field(acc, k);
+        wtotal = acc + (static_cast<uint64_t>(nvalid - others) << (16 * (V - 1)));
     }
 
-    // Adds each wave's per-class offset to its ranks; tile class sizes to tot.
-    __device__ __forceinline__ void block_ranks(uint32_t (*wt)[V], int wave, int lane, uint32_t (&tot)[V]) {
-        if (lane == 0)
-#pragma unroll
-            for (int k = 0; k < V; ++k) wt[wave][k] = wtotal[k];
+    // Adds each wave's per-class offset to its ranks; returns the tile's
+    // packed class sizes.
+    __device__ __forceinline__ uint64_t block_ranks(uint64_t *wt, int wave, int lane) {
+        if (lane == 0) wt[wave] = wtotal;
         __syncthreads();
-        uint32_t before[V];
+        uint64_t before = 0, tot = 0;
 #pragma unroll
-        for (int k = 0; k < V; ++k) before[k] = tot[k] = 0;
-#pragma unroll
-        for (int w = 0; w < kWaves; ++w)
-#pragma unroll
-            for (int k = 0; k < V; ++k) {
-                const uint32_t x = wt[w][k];
-                before[k] += w < wave ? x : 0u;
-                tot[k] += x;
-            }
+        for (int w = 0; w < kWaves; ++w) {
+            const uint64_t x = wt[w];
+            before += w < wave ? x : 0ull;
+            tot += x;
+        }
 #pragma unroll
         for (int r = 0; r < ROWS; ++r)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) rank[r][q] += pick<V>(before, cls(r, q));
+            for (int q = 0; q < 4; ++q) rank[r][q] += field(before, cls(r, q));
+        return tot;
     }
 };
 
@@ -261,16 +280,11 @@ __global__ __launch_bounds__(256) void flatv_count_kernel(VArgs a, Cls cl) {
     for (int64_t t = t0; t < t1; ++t) {
         const int64_t lo = t * kTile;
         const int64_t hi = lo + kTile < a.n ? lo + kTile : a.n;
-        uint32_t cnt[V - 1];
-#pragma unroll
-        for (int k = 0; k < V - 1; ++k) cnt[k] = 0;
+        uint64_t cnt = 0;   // packed per-class counts of the tile
         for (int c = 0; c < kChunks; ++c) {
             WT chunk;
             chunk.load(a.keys, a.n, lo + c * WT::kSize, lo, hi, cl, !Cls::kUsesBytes, 0, lane);
-            uint32_t cc[V];
-            chunk.wave_counts(cc);
-#pragma unroll
-            for (int k = 0; k < V - 1; ++k) cnt[k] += cc[k];
+            cnt += chunk.wave_counts();
         }
         if (lane < V - 1) {
             uint64_t mine = run[0];
@@ -279,7 +293,7 @@ __global__ __launch_bounds__(256) void flatv_count_kernel(VArgs a, Cls cl) {
             a.desc[t * 4 + lane] = mine;
         }
 #pragma unroll
-        for (int k = 0; k < V - 1; ++k) run[k] += cnt[k];
+        for (int k = 0; k < V - 1; ++k) run[k] += WT::field(cnt, k);
     }
     if (lane < V - 1 && w < kVCountWaves) {
         uint64_t mine = run[0];
@@ -345,7 +359,7 @@ __global__ __launch_bounds__(kVBlockThreads) void flatv_scatter_kernel(VArgs a, 
     using T = TileV<kVBlockThreads, kVRows, V>;
     constexpr int kTile = T::kSize;
     __shared__ uint32_t stage[kTile];
-    __shared__ uint32_t wt[T::kWaves][V];
+    __shared__ uint64_t wt[T::kWaves];
 
     const int tid = threadIdx.x;
     const int wave = wave_id();
@@ -372,13 +386,14 @@ __global__ __launch_bounds__(kVBlockThreads) void flatv_scatter_kernel(VArgs a, 
 
     T tile;
     tile.load(a.keys, a.n, lo, lo, hi, cl, a.need_keys != 0, wave, lane);
-    tile.wave_ranks();
-    uint32_t tot[V];
-    tile.block_ranks(wt, wave, lane, tot);
-    uint32_t sbase[V];   // stage offset of each class inside the tile
-    sbase[0] = 0;
+    tile.wave_ranks(lane);
+    const uint64_t ptot = tile.block_ranks(wt, wave, lane);
+    uint32_t tot[V], sbase[V];   // class sizes and stage offsets inside the tile
 #pragma unroll
-    for (int k = 1; k < V; ++k) sbase[k] = sbase[k - 1] + tot[k - 1];
+    for (int k = 0; k < V; ++k) {
+        tot[k] = T::field(ptot, k);
+        sbase[k] = k == 0 ? 0u : sbase[k - 1] + tot[k - 1];
+    }
 
     Idx *out_idx = static_cast<Idx *>(a.out_idx);
 #pragma unroll
