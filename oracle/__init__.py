@@ -48,6 +48,7 @@ def _load():
             "ixo_scatter_checked": [P, i64, P, P, i64, i64, P],
             "ixo_get_smallest_pairs": [i64, i64, P, P, i64, P, P, P],
             "ixo_partition_v": [P, i64, i32, i32, P, P, P, P, P],
+            "ixo_partition2L_rows": [P, i32, i64, P, i64, i32, i64, P, i32, P, P, P, P],
             "ixo_partition2": [P, i32, i64, i32, i64, i64, f32, P, i32, P, P, P],
             "ixo_sgm_sum": [P, P, i64, P],
             "ixo_mk_sgm_descr": [P, i64, P, P, i64],
@@ -152,6 +153,29 @@ def partition2L(keys: np.ndarray, shape: np.ndarray, p: Pred,
     _check(_load().ixo_partition2L(_ptr(keys), _key_t(keys), n, _ptr(shape), m,
                                    *_pred_args(p), mode, _ptr(ys), _ptr(idx),
                                    _ptr(seg), _ptr(flags)), "partition2L")
+    if mode == MODE_FILTER:
+        ys = ys[: int(seg.sum())].copy()
+    return ys, idx, seg, flags
+
+
+ROW_LT, ROW_MOD = 0, 1
+
+
+def partition2L_rows(keys: np.ndarray, shape: np.ndarray, row_kind: int, d: int = 1,
+                     s_rows: Optional[np.ndarray] = None, mode: int = MODE_PARTITION):
+    """partition2L with a predicate of the row number: ROW_LT (x < s_rows[k])
+    or ROW_MOD (floor-mod(x, d) == floor-mod(k, d)).  Returns as partition2L."""
+    keys = np.ascontiguousarray(keys)
+    shape = np.ascontiguousarray(shape, dtype=np.int64)
+    n, m = len(keys), len(shape)
+    sr = None if s_rows is None else np.ascontiguousarray(s_rows, dtype=np.float32)
+    ys = np.zeros(n, dtype=keys.dtype)
+    idx = np.zeros(n, dtype=np.int64)
+    seg = np.zeros(m, dtype=np.int64)
+    flags = np.zeros(n, dtype=np.uint8)
+    _check(_load().ixo_partition2L_rows(_ptr(keys), _key_t(keys), n, _ptr(shape), m, row_kind, d,
+                                        _ptr(sr), mode, _ptr(ys), _ptr(idx), _ptr(seg), _ptr(flags)),
+           "partition2L_rows")
     if mode == MODE_FILTER:
         ys = ys[: int(seg.sum())].copy()
     return ys, idx, seg, flags

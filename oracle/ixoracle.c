@@ -503,6 +503,48 @@ int ixo_partition2L(const void *xs, int key_t, int64_t n, const int64_t *shape,
     return rc;
 }
 
+/* partition2L with predicates that depend on the segment number (Section 1:
+ * segmented two-way partitioning filters or partitions each row of the jagged
+ * array by a predicate of the row number k):
+ *   IXO_ROW_LT:  f32 keys, p_k(x) = x < s_rows[k];
+ *   IXO_ROW_MOD: int32 keys, p_k(x) = floor-mod(x, d) == floor-mod(k, d).
+ * The flags cs are computed row by row, then partition2L runs on them. */
+enum { IXO_ROW_LT = 0, IXO_ROW_MOD = 1 };
+
+int ixo_partition2L_rows(const void *xs, int key_t, int64_t n, const int64_t *shape,
+                         int64_t m, int row_kind, int64_t d, const float *s_rows, int mode,
+                         void *ys, int64_t *indices, int64_t *seg_split, uint8_t *flags_out) {
+    if (n < 0 || m < 0 || (n > 0 && !xs)) return -1;
+    if (row_kind == IXO_ROW_LT ? (key_t != IXO_F32 || (m > 0 && !s_rows))
+                               : (row_kind != IXO_ROW_MOD || key_t != IXO_I32 || d < 1))
+        return -1;
+    int64_t total = 0;
+    for (int64_t k = 0; k < m; k++) {
+        if (shape[k] < 0) return -1;
+        total += shape[k];
+    }
+    if (total != n) return -1;
+    uint8_t *cs = malloc((size_t)(n > 0 ? n : 1));
+    if (!cs) return -2;
+    int rc = 0;
+    int64_t o = 0;
+    int64_t kb = key_bytes(key_t);
+    for (int64_t k = 0; k < m && rc == 0; k++) {
+        const void *row = (const char *)xs + o * kb;
+        if (row_kind == IXO_ROW_LT)
+            rc = ixo_map_pred(row, key_t, shape[k], IXO_PRED_LT, 1, 0, s_rows[k], NULL, cs + o);
+        else
+            rc = ixo_map_pred(row, key_t, shape[k], IXO_PRED_MOD_EQ, d, floor_mod(k, d), 0.f, NULL,
+                              cs + o);
+        o += shape[k];
+    }
+    if (rc == 0)
+        rc = ixo_partition2L(xs, key_t, n, shape, m, IXO_PRED_FLAGS, 1, 0, 0.f, cs, mode, ys,
+                             indices, seg_split, flags_out);
+    free(cs);
+    return rc;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Property checkers (Section 2.3, figure "Array Properties").              */
 /* Each writes a verdict {holds, first_violation, aux} as three int64:       */

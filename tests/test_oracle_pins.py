@@ -483,3 +483,42 @@ def test_partition_v_two_classes_is_partition2():
 def test_partition_v_rejects_unsorted_thresholds():
     with pytest.raises(ValueError):
         O.partition_v(np.zeros(4, np.float32), 3, O.CLASS_THRESH, (0.5, 0.2))
+
+
+# --------------------------------------- predicates of the row number (partition2L) ---
+
+def test_partition2L_row_predicates_against_numpy():
+    """Each row partitioned by its own predicate: numpy stable argsort of the
+    negated flags, row by row; equal thresholds reduce to partition2L."""
+    g = np.random.default_rng(101)
+    shape = W.segment_sizes(60, 102, median_log2=6, sigma_log2=1.5, empty_frac=0.2)
+    n = int(shape.sum())
+    xf = g.random(n, dtype=np.float32)
+    s_rows = g.random(len(shape)).astype(np.float32)
+    xi = W.int_keys(n, 103) - (1 << 30)
+    off = np.concatenate([[0], np.cumsum(shape)])
+    for mode in (O.MODE_PARTITION, O.MODE_FILTER):
+        for kind, x in ((O.ROW_LT, xf), (O.ROW_MOD, xi)):
+            ys, idx, seg, fl = O.partition2L_rows(x, shape, kind, 3, s_rows, mode)
+            exp_idx = np.full(n, -1, dtype=np.int64)
+            kept_before = 0
+            exp_ys = []
+            for k in range(len(shape)):
+                row = x[off[k]:off[k + 1]]
+                c = row < s_rows[k] if kind == O.ROW_LT else np.mod(row.astype(np.int64), 3) == k % 3
+                order = np.argsort(~c, kind="stable")
+                if mode == O.MODE_PARTITION:
+                    exp_idx[off[k] + order] = off[k] + np.arange(len(row))
+                    exp_ys.append(row[order])
+                else:
+                    kept = np.flatnonzero(c)
+                    exp_idx[off[k] + kept] = kept_before + np.arange(len(kept))
+                    exp_ys.append(row[kept])
+                    kept_before += len(kept)
+                assert seg[k] == c.sum()
+            assert np.array_equal(idx, exp_idx)
+            assert np.array_equal(ys.view(np.uint32), np.concatenate(exp_ys).view(np.uint32))
+    same = np.full(len(shape), 0.4, dtype=np.float32)
+    a = O.partition2L_rows(xf, shape, O.ROW_LT, s_rows=same)
+    b = O.partition2L(xf, shape, O.Pred.lt(0.4))
+    assert all(np.array_equal(u, v) for u, v in zip(a, b))
