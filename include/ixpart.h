@@ -71,8 +71,15 @@ enum { IXP_I32 = 0, IXP_I64 = 1, IXP_F32 = 2, IXP_U8 = 3 };
  *                    NaN gives false.
  *   IXP_PRED_FLAGS:  keys I32 or F32 (moved as bits); p(i) = flags[i] != 0,
  *                    `flags` a device u8 array of length n (partition2L's csL;
- *                    NULL allowed when n == 0). */
-enum { IXP_PRED_MOD_EQ = 0, IXP_PRED_LT = 1, IXP_PRED_FLAGS = 2 };
+ *                    NULL allowed when n == 0).
+ * Predicates of the row number k (segmented calls only; Section 1: segmented
+ * partitioning by predicates that depend on the segment number):
+ *   IXP_PRED_LT_ROW:  keys F32; p_k(x) = (x < row_s[k]), `row_s` a device
+ *                     f32 array of length m;
+ *   IXP_PRED_MOD_ROW: keys I32; p_k(x) = (x mod d == k mod d), floor moduli,
+ *                     1 <= d < 2^32. */
+enum { IXP_PRED_MOD_EQ = 0, IXP_PRED_LT = 1, IXP_PRED_FLAGS = 2,
+       IXP_PRED_LT_ROW = 3, IXP_PRED_MOD_ROW = 4 };
 typedef struct {
     int32_t kind;
     int32_t reserved0;
@@ -81,6 +88,7 @@ typedef struct {
     float s;
     int32_t reserved1;
     const uint8_t *flags;   /* device */
+    const float *row_s;     /* device, IXP_PRED_LT_ROW */
 } ixp_pred;
 
 /* IXP_MODE_PARTITION: FiltPart with p^f = true and partition predicate p --
@@ -191,6 +199,21 @@ int ixp_segmented_partition(const void *keys, int32_t key_t, int64_t n,
                             void *out_idx, int32_t idx_t, int64_t *d_seg_split,
                             uint8_t *d_flags_out, const ixp_tuning *tune,
                             void *ws, size_t ws_bytes, void *stream);
+
+/* The segment helpers of Section 2.1 (figure "Running Examples", right) as
+ * device outputs, for rows of sizes d_shape[0..m) (>= 0, summing to n; a bad
+ * shape is reported by ixp_read_error as IXP_EINVAL and nothing is written):
+ *   ixp_mk_ii:        out[i] = k for every i of row k (mkII), out_t IXP_I32
+ *                     or IXP_I64;
+ *   ixp_mk_sgm_descr: d_out[o_k] = d_xs[k] for every non-empty row k, 0 at
+ *                     every other position (mkSgmDescr), int64.
+ * Workspace: ixp_mk_ii_workspace(n, m) bytes, 16-byte aligned.  3 kernels. */
+size_t ixp_mk_ii_workspace(int64_t n, int64_t m);
+int ixp_mk_ii(const int64_t *d_shape, int64_t m, int64_t n, void *out,
+              int32_t out_t, void *ws, size_t ws_bytes, void *stream);
+int ixp_mk_sgm_descr(const int64_t *d_shape, int64_t m, int64_t n,
+                     const int64_t *d_xs, int64_t *d_out, void *ws,
+                     size_t ws_bytes, void *stream);
 
 /* Blocking: times every candidate tiling on the given arguments (which it
  * overwrites) and stores the fastest in *best (and its time in *best_ms). */

@@ -15,7 +15,7 @@ LIB_PATH = os.environ.get("IXP_LIB", os.path.join(_HERE, "libixpart.so"))
 IXP_OK, IXP_EINVAL, IXP_ENOMEM, IXP_EHIP, IXP_EUNSUPPORTED, IXP_EWORKSPACE, IXP_EDEVICE = \
     0, -1, -2, -3, -4, -5, -6
 I32, I64, F32, U8 = 0, 1, 2, 3
-PRED_MOD_EQ, PRED_LT, PRED_FLAGS = 0, 1, 2
+PRED_MOD_EQ, PRED_LT, PRED_FLAGS, PRED_LT_ROW, PRED_MOD_ROW = 0, 1, 2, 3, 4
 MODE_PARTITION, MODE_FILTER = 0, 1
 RANGE, MONO, INJ, BIJ, FILTPART = 1, 2, 4, 8, 16
 CLASS_MOD, CLASS_THRESH, CLASS_BYTES = 0, 1, 2
@@ -25,7 +25,7 @@ MONO_LE, MONO_LT, MONO_GE, MONO_GT = 0, 1, 2, 3
 class ixp_pred(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("reserved0", ctypes.c_int32),
                 ("d", ctypes.c_int64), ("r", ctypes.c_int64), ("s", ctypes.c_float),
-                ("reserved1", ctypes.c_int32), ("flags", ctypes.c_void_p)]
+                ("reserved1", ctypes.c_int32), ("flags", ctypes.c_void_p), ("row_s", ctypes.c_void_p)]
 
 
 class ixp_classes(ctypes.Structure):
@@ -71,6 +71,9 @@ SIGNATURES = {
     "ixp_partition_workspace": (_SZ, [_I64]),
     "ixp_partition": (ctypes.c_int, [_P, _I32, _I64, _PP, _I32, _P, _P, _I32, _P, _P, _SZ, _P]),
     "ixp_partition_v_workspace": (_SZ, [_I64]),
+    "ixp_mk_ii_workspace": (_SZ, [_I64, _I64]),
+    "ixp_mk_ii": (ctypes.c_int, [_P, _I64, _I64, _P, _I32, _P, _SZ, _P]),
+    "ixp_mk_sgm_descr": (ctypes.c_int, [_P, _I64, _I64, _P, _P, _P, _SZ, _P]),
     "ixp_partition_v": (ctypes.c_int, [_P, _I32, _I64, _PC, _P, _P, _I32, _P, _P, _SZ, _P]),
     "ixp_segmented_workspace": (_SZ, [_I64, _I64, _PT]),
     "ixp_segmented_partition": (ctypes.c_int, [_P, _I32, _I64, _P, _I64, _PP, _I32, _P, _P,

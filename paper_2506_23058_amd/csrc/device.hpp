@@ -75,6 +75,8 @@ struct PredModEq {
     uint64_t M;
     uint32_t d;
     int64_t r;
+    // the predicate of row k (this one does not depend on the row)
+    __device__ __forceinline__ PredModEq at_row(int64_t) const { return *this; }
     __device__ __forceinline__ bool operator()(uint32_t bits, uint8_t) const {
         const int32_t x = static_cast<int32_t>(bits);
         const uint32_t a = x < 0 ? 0u - bits : bits;   // |x|, 2^31 for INT_MIN
@@ -88,6 +90,7 @@ struct PredModEq {
 struct PredLt {
     static constexpr bool kUsesFlags = false;
     float s;
+    __device__ __forceinline__ PredLt at_row(int64_t) const { return *this; }
     __device__ __forceinline__ bool operator()(uint32_t bits, uint8_t) const {
         return __uint_as_float(bits) < s;
     }
@@ -97,7 +100,33 @@ struct PredLt {
 struct PredFlags {
     static constexpr bool kUsesFlags = true;
     const uint8_t *flags;
+    __device__ __forceinline__ PredFlags at_row(int64_t) const { return *this; }
     __device__ __forceinline__ bool operator()(uint32_t, uint8_t f) const { return f != 0; }
+};
+
+// Predicates of the row number k (segmented calls): at_row(k) fixes k and
+// returns a predicate of the key alone.
+// x < row_s[k] in IEEE single precision.
+struct PredLtRow {
+    static constexpr bool kUsesFlags = false;
+    const float *row_s;
+    float s;
+    __device__ __forceinline__ PredLtRow at_row(int64_t k) const { return PredLtRow{row_s, row_s[k]}; }
+    __device__ __forceinline__ bool operator()(uint32_t bits, uint8_t) const {
+        return __uint_as_float(bits) < s;
+    }
+};
+
+// x mod d == k mod d, floor moduli (k >= 0, so k mod d is the remainder).
+struct PredModRow {
+    static constexpr bool kUsesFlags = false;
+    PredModEq eq;
+    __device__ __forceinline__ PredModRow at_row(int64_t k) const {
+        PredModRow p = *this;
+        p.eq.r = static_cast<int64_t>(static_cast<uint64_t>(k) % eq.d);
+        return p;
+    }
+    __device__ __forceinline__ bool operator()(uint32_t bits, uint8_t f) const { return eq(bits, f); }
 };
 
 // ---------------------------------------------------------- tile descriptors --

@@ -354,6 +354,7 @@ extern "C" int ixp_partition(const void *keys, int32_t key_t, int64_t n, const i
     HostPred hp;
     int rc = check_pred(pred, key_t, &hp, n);
     if (rc != IXP_OK) return rc;
+    if (is_row_pred(hp.kind)) return IXP_EINVAL;   // a flat array has no rows
     const bool need_keys = hp.kind != IXP_PRED_FLAGS || out_keys != nullptr;
     if (n > 0 && need_keys && !keys) return IXP_EINVAL;
     if (!ws || ws_bytes < ixp_partition_workspace(n)) return IXP_EWORKSPACE;

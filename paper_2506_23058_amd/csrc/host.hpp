@@ -31,9 +31,11 @@ struct HostPred {
     int64_t r;
     float s;
     const uint8_t *flags;
+    const float *row_s;
 };
 
-// `n` elements are tested: a flag array may be NULL only when n == 0.
+// `n` elements are tested: a flag or row array may be NULL only when n == 0.
+// Row predicates are accepted here; calls without rows reject them.
 inline int check_pred(const ixp_pred *p, int32_t key_t, HostPred *out, int64_t n) {
     if (!p) return IXP_EINVAL;
     out->kind = p->kind;
@@ -42,7 +44,9 @@ inline int check_pred(const ixp_pred *p, int32_t key_t, HostPred *out, int64_t n
     out->r = p->r;
     out->d = 1;
     out->M = 0;
+    out->row_s = p->row_s;
     switch (p->kind) {
+    case IXP_PRED_MOD_ROW:
     case IXP_PRED_MOD_EQ:
         if (key_t != IXP_I32) return key_t == IXP_I64 ? IXP_EUNSUPPORTED : IXP_EINVAL;
         if (p->d < 1 || p->d > 0xFFFFFFFFll) return IXP_EINVAL;
@@ -51,6 +55,9 @@ inline int check_pred(const ixp_pred *p, int32_t key_t, HostPred *out, int64_t n
         return IXP_OK;
     case IXP_PRED_LT:
         return key_t == IXP_F32 ? IXP_OK : IXP_EINVAL;
+    case IXP_PRED_LT_ROW:
+        if (key_t != IXP_F32) return IXP_EINVAL;
+        return (p->row_s || n == 0) ? IXP_OK : IXP_EINVAL;
     case IXP_PRED_FLAGS:
         if (key_t != IXP_I32 && key_t != IXP_F32) return IXP_EINVAL;
         return (p->flags || n == 0) ? IXP_OK : IXP_EINVAL;
@@ -58,6 +65,8 @@ inline int check_pred(const ixp_pred *p, int32_t key_t, HostPred *out, int64_t n
         return IXP_EINVAL;
     }
 }
+
+inline bool is_row_pred(int kind) { return kind == IXP_PRED_LT_ROW || kind == IXP_PRED_MOD_ROW; }
 
 // Number of compute units of the current device, cached per device.
 int device_cus();

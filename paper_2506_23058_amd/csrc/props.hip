@@ -870,6 +870,7 @@ extern "C" int ixp_check_props(const void *x, int32_t x_t, int64_t n, uint32_t m
             return IXP_EINVAL;
         int rc = check_pred(&pa->fp_pred, pa->fp_key_t, &hp, n);
         if (rc != IXP_OK) return rc;
+        if (is_row_pred(hp.kind)) return IXP_EINVAL;
         if (!pa->fp_src) return IXP_EINVAL;
         if (!aligned(pa->fp_src, 4) || !aligned(pa->fp_dst, 4) || !aligned(pa->fp_split, 8)) return IXP_EINVAL;
     }

@@ -227,7 +227,7 @@ __global__ __launch_bounds__(256) void seg_count_kernel(SegArgs a, Pred pred) {
         const int64_t b = d.base + (c << 10);
         if (b >= d.hi) continue;
         WT chunk;
-        chunk.load(a.keys, a.n, b, d.lo, d.hi, pred, !Pred::kUsesFlags, 0, lane);
+        chunk.load(a.keys, a.n, b, d.lo, d.hi, pred.at_row(d.row), !Pred::kUsesFlags, 0, lane);
         const uint32_t cnt = chunk.wave_count();
         if (lane == 0 && cnt) atomicAdd(a.counts + it, static_cast<unsigned long long>(cnt));
     }
@@ -343,7 +343,7 @@ __global__ __launch_bounds__(BLOCK) void seg_main_kernel(SegArgs a, Pred pred) {
 
         T tile;
         if (T::wave_live(base, lo, hi, wave))   // waves past a short item load nothing
-            tile.load(a.keys, a.n, base, lo, hi, pred, a.need_keys != 0, wave, lane);
+            tile.load(a.keys, a.n, base, lo, hi, pred.at_row(d.row), a.need_keys != 0, wave, lane);
         tile.wave_ranks();
         const uint32_t tcount = tile.block_ranks(wtot, wave, lane);
 
@@ -401,6 +401,42 @@ __global__ __launch_bounds__(BLOCK) void seg_main_kernel(SegArgs a, Pred pred) {
         }
         __syncthreads();   // LDS is reused by the next item
     }
+}
+
+// ------------------------------------------------------------ shape tools --
+// The segment helpers of Section 2.1 as device outputs, over the item records
+// (each item knows its row; the first item of a non-empty row starts at o_k):
+//   mkII:       ii[i] = k for o_k <= i < o_k + s_k;
+//   mkSgmDescr: out[o_k] = xs[k] for every non-empty row k, 0 elsewhere.
+// Workgroup w takes items w, w + grid, ...; consecutive threads write
+// consecutive elements.
+template <int TOOL, class Out>
+__global__ __launch_bounds__(256) void seg_fill_kernel(SegArgs a, Out *out, const int64_t *xs) {
+    if (*a.err != 0) return;
+    const int64_t nitems = *a.num_items;
+    for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const SegItem d = a.items[it];
+        const bool first = (d.kind & 2) != 0;
+        const Out head = TOOL == 0 ? static_cast<Out>(d.row) : static_cast<Out>(first ? xs[d.row] : 0);
+        for (int64_t i = d.lo + threadIdx.x; i < d.hi; i += 256) {
+            Out v;
+            if (TOOL == 0) v = static_cast<Out>(d.row);
+            else v = i == d.lo ? head : static_cast<Out>(0);
+            stream_store(out + i, v);
+        }
+    }
+}
+
+template <int TOOL, class Out>
+int launch_tool(const SegArgs &a, Out *out, const int64_t *xs, hipStream_t st) {
+    IXP_LAUNCH("seg_setup", seg_setup_kernel, dim3(1), dim3(kSetupThreads), 0, st, a);
+    const uint32_t rblocks = static_cast<uint32_t>(ceil_div(a.m > 0 ? a.m : 1, 256));
+    IXP_LAUNCH("seg_items", seg_items_kernel, dim3(rblocks), dim3(256), 0, st, a);
+    const int64_t cap = static_cast<int64_t>(device_cus()) * 16;
+    const int64_t grid = a.max_items < cap ? (a.max_items > 0 ? a.max_items : 1) : cap;
+    IXP_LAUNCH(TOOL == 0 ? "seg_mk_ii" : "seg_mk_sgm_descr", (seg_fill_kernel<TOOL, Out>),
+               dim3(static_cast<uint32_t>(grid)), dim3(256), 0, st, a, out, xs);
+    return launch_status();
 }
 
 // ----------------------------------------------------------------- launch --
@@ -499,6 +535,8 @@ size_t seg_workspace(int64_t n, int64_t m, const SegGeom &g) {
            round_up(static_cast<size_t>(mi + 1) * 8, 256) + static_cast<size_t>(mi) * 8;
 }
 
+void set_layout(int64_t n, int64_t m, const int64_t *d_shape, const SegGeom &g, void *ws, SegArgs *a);
+
 int prepare(const void *keys, int32_t key_t, int64_t n, const int64_t *d_shape, int64_t m,
             const ixp_pred *pred, int32_t mode, void *out_keys, void *out_idx, int32_t idx_t,
             int64_t *d_seg_split, uint8_t *d_flags_out, const SegGeom &g, void *ws,
@@ -523,16 +561,31 @@ int prepare(const void *keys, int32_t key_t, int64_t n, const int64_t *d_shape, 
         !aligned(ws, 16))
         return IXP_EINVAL;
     if (hp->kind == IXP_PRED_FLAGS && !aligned(hp->flags, 4)) return IXP_EINVAL;
-    char *w = static_cast<char *>(ws);
-    const size_t rows_bytes = round_up(static_cast<size_t>(m + 1) * 8, 256);
+    if (hp->kind == IXP_PRED_LT_ROW && !aligned(hp->row_s, 4)) return IXP_EINVAL;
+    set_layout(n, m, d_shape, g, ws, a);
     a->keys = static_cast<const uint32_t *>(keys);
-    a->n = n;
-    a->shape = d_shape;
-    a->m = m;
     a->out_keys = static_cast<uint32_t *>(out_keys);
     a->out_idx = out_idx;
     a->seg_split = d_seg_split;
     a->flags_out = d_flags_out;
+    a->mode = mode;
+    a->need_keys = need_keys ? 1 : 0;
+    return IXP_OK;
+}
+
+// Shape-derived part of the arguments: the workspace layout (row offsets,
+// item records, item counts and their scan) for n elements in m rows.
+void set_layout(int64_t n, int64_t m, const int64_t *d_shape, const SegGeom &g, void *ws, SegArgs *a) {
+    char *w = static_cast<char *>(ws);
+    const size_t rows_bytes = round_up(static_cast<size_t>(m + 1) * 8, 256);
+    a->keys = nullptr;
+    a->n = n;
+    a->shape = d_shape;
+    a->m = m;
+    a->out_keys = nullptr;
+    a->out_idx = nullptr;
+    a->seg_split = nullptr;
+    a->flags_out = nullptr;
     a->err = reinterpret_cast<int32_t *>(w + 4);
     a->num_items = reinterpret_cast<int64_t *>(w + 8);
     a->offsets = reinterpret_cast<int64_t *>(w + kSegHeader);
@@ -546,15 +599,16 @@ int prepare(const void *keys, int32_t key_t, int64_t n, const int64_t *d_shape, 
     a->tile = g.tile();
     a->tile_shift = 0;
     while ((int64_t{1} << a->tile_shift) < a->tile) ++a->tile_shift;
-    a->mode = mode;
-    a->need_keys = need_keys ? 1 : 0;
-    return IXP_OK;
+    a->mode = IXP_MODE_PARTITION;
+    a->need_keys = 0;
 }
 
 int run(const SegArgs &a, const HostPred &hp, const SegGeom &g, int mode, int idx_t, hipStream_t st) {
     switch (hp.kind) {
     case IXP_PRED_MOD_EQ: return launch_all(a, PredModEq{hp.M, hp.d, hp.r}, g, mode, idx_t, st);
     case IXP_PRED_LT: return launch_all(a, PredLt{hp.s}, g, mode, idx_t, st);
+    case IXP_PRED_LT_ROW: return launch_all(a, PredLtRow{hp.row_s, 0.f}, g, mode, idx_t, st);
+    case IXP_PRED_MOD_ROW: return launch_all(a, PredModRow{PredModEq{hp.M, hp.d, 0}}, g, mode, idx_t, st);
     default: return launch_all(a, PredFlags{hp.flags}, g, mode, idx_t, st);
     }
 }
@@ -702,4 +756,35 @@ extern "C" int ixp_graph_destroy(ixp_graph g) {
     if (g->graph && hipGraphDestroy(g->graph) != hipSuccess) rc = IXP_EHIP;
     delete g;
     return rc;
+}
+
+extern "C" size_t ixp_mk_ii_workspace(int64_t n, int64_t m) {
+    if (n < 0 || m < 0) return 0;
+    return seg_workspace(n, m, geom_from(nullptr));
+}
+
+extern "C" int ixp_mk_ii(const int64_t *d_shape, int64_t m, int64_t n, void *out, int32_t out_t, void *ws,
+                         size_t ws_bytes, void *stream) {
+    if (n < 0 || m < 0 || m > 0x7FFFFFFFll || (m > 0 && !d_shape) || (n > 0 && !out)) return IXP_EINVAL;
+    if (out_t != IXP_I32 && out_t != IXP_I64) return IXP_EINVAL;
+    const SegGeom g = geom_from(nullptr);
+    if (!ws || ws_bytes < seg_workspace(n, m, g)) return IXP_EWORKSPACE;
+    if (!aligned(d_shape, 8) || !aligned(out, out_t == IXP_I32 ? 4 : 8) || !aligned(ws, 16)) return IXP_EINVAL;
+    SegArgs a;
+    set_layout(n, m, d_shape, g, ws, &a);
+    hipStream_t st = as_stream(stream);
+    return out_t == IXP_I32 ? launch_tool<0>(a, static_cast<int32_t *>(out), nullptr, st)
+                            : launch_tool<0>(a, static_cast<int64_t *>(out), nullptr, st);
+}
+
+extern "C" int ixp_mk_sgm_descr(const int64_t *d_shape, int64_t m, int64_t n, const int64_t *d_xs,
+                                int64_t *d_out, void *ws, size_t ws_bytes, void *stream) {
+    if (n < 0 || m < 0 || m > 0x7FFFFFFFll || (m > 0 && (!d_shape || !d_xs)) || (n > 0 && !d_out))
+        return IXP_EINVAL;
+    const SegGeom g = geom_from(nullptr);
+    if (!ws || ws_bytes < seg_workspace(n, m, g)) return IXP_EWORKSPACE;
+    if (!aligned(d_shape, 8) || !aligned(d_xs, 8) || !aligned(d_out, 8) || !aligned(ws, 16)) return IXP_EINVAL;
+    SegArgs a;
+    set_layout(n, m, d_shape, g, ws, &a);
+    return launch_tool<1>(a, d_out, d_xs, as_stream(stream));
 }

@@ -20,12 +20,15 @@ _IDX_T = {torch.int32: L.I32, torch.int64: L.I64}
 @dataclass(frozen=True)
 class Pred:
     """Predicate p of partition2 (Section 2.1): MOD_EQ (floor-mod of an int32
-    key by d equals r), LT (f32 key < s) or FLAGS (a u8 tensor, nonzero = true)."""
+    key by d equals r), LT (f32 key < s) or FLAGS (a u8 tensor, nonzero = true);
+    for segmented calls also predicates of the row number k: LT_ROW (x <
+    row_s[k], an f32 tensor of m thresholds) and MOD_ROW (x mod d == k mod d)."""
     kind: int
     d: int = 1
     r: int = 0
     s: float = 0.0
     flags: Optional[torch.Tensor] = None
+    row_s: Optional[torch.Tensor] = None
 
     @staticmethod
     def mod_eq(d: int, r: int) -> "Pred":
@@ -41,6 +44,14 @@ class Pred:
             flags = flags.view(torch.uint8)
         return Pred(L.PRED_FLAGS, flags=flags.contiguous())
 
+    @staticmethod
+    def lt_rows(row_s: torch.Tensor) -> "Pred":
+        return Pred(L.PRED_LT_ROW, row_s=row_s.to(torch.float32).contiguous())
+
+    @staticmethod
+    def mod_rows(d: int) -> "Pred":
+        return Pred(L.PRED_MOD_ROW, d=int(d))
+
     def c(self) -> L.ixp_pred:
         p = L.ixp_pred()
         p.kind = self.kind
@@ -48,6 +59,7 @@ class Pred:
         p.r = self.r
         p.s = self.s
         p.flags = self.flags.data_ptr() if self.flags is not None else None
+        p.row_s = self.row_s.data_ptr() if self.row_s is not None else None
         return p
 
 
@@ -236,6 +248,39 @@ def segmented_partition(keys: torch.Tensor, shape: torch.Tensor, pred: Pred,
         tp, _ptr(ws), ws.numel(), _stream_ptr(keys.device))
     L.check(rc, "ixp_segmented_partition")
     return out_keys, out_idx, seg_split, flags
+
+
+def mk_ii(shape: torch.Tensor, n: int, out_dtype=torch.int64, ws_tag: str = "shape_tools") -> torch.Tensor:
+    """mkII: the row number of every element of rows of the given sizes."""
+    _check_dev(shape)
+    shape = shape.contiguous()
+    m = shape.numel()
+    out = torch.empty(n, dtype=out_dtype, device=shape.device)
+    ws = workspace(L.lib().ixp_mk_ii_workspace(n, m), shape.device, ws_tag)
+    rc = L.lib().ixp_mk_ii(_ptr(shape), m, n, _ptr(out), _IDX_T[out_dtype], _ptr(ws), ws.numel(),
+                           _stream_ptr(shape.device))
+    L.check(rc, "ixp_mk_ii")
+    return out
+
+
+def mk_sgm_descr(shape: torch.Tensor, xs: torch.Tensor, n: int, ws_tag: str = "shape_tools") -> torch.Tensor:
+    """mkSgmDescr: xs[k] at the first position of every non-empty row k, 0 elsewhere."""
+    _check_dev(shape, xs)
+    shape = shape.contiguous()
+    xs = xs.contiguous().to(torch.int64)
+    m = shape.numel()
+    out = torch.empty(n, dtype=torch.int64, device=shape.device)
+    ws = workspace(L.lib().ixp_mk_ii_workspace(n, m), shape.device, ws_tag)
+    rc = L.lib().ixp_mk_sgm_descr(_ptr(shape), m, n, _ptr(xs), _ptr(out), _ptr(ws), ws.numel(),
+                                  _stream_ptr(shape.device))
+    L.check(rc, "ixp_mk_sgm_descr")
+    return out
+
+
+def shape_tools_error(ws_tag: str = "shape_tools", device="cuda:0") -> int:
+    """Blocking: the error recorded by the last mk_ii / mk_sgm_descr call."""
+    ws = _ws_cache.get((str(torch.device(device)), ws_tag))
+    return 0 if ws is None else L.lib().ixp_read_error(_ptr(ws), _stream_ptr(ws.device))
 
 
 def segmented_error(ws_tag: str = "segmented", device="cuda:0") -> int:

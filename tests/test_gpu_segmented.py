@@ -173,3 +173,34 @@ def test_rows_of_millions_of_elements_among_small_rows():
     run_both(keys, shape)
     run_both(keys, shape, tune=(1024, 4))
     run_both(keys, shape, mode=1)
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("tune", [None, (256, 2), (1024, 4)])
+def test_predicates_of_the_row_number(mode, tune):
+    """partition2L with predicates of the row number k: x < s[k] (per-row
+    thresholds) and x mod 3 == k mod 3, against the row-predicate oracle."""
+    shape = W.segment_sizes(3000, 111, median_log2=9, sigma_log2=2.0, empty_frac=0.15)
+    n = int(shape.sum())
+    g = np.random.default_rng(112)
+    s_rows = g.random(len(shape)).astype(np.float32)
+    xf = W.f32_uniform(n, 113)
+    xi = W.int_keys(n, 114) - (1 << 30)
+    st = torch.from_numpy(shape).to(DEV)
+    for pred, x, kind in ((P.Pred.lt_rows(torch.from_numpy(s_rows).to(DEV)), xf, O.ROW_LT),
+                          (P.Pred.mod_rows(3), xi, O.ROW_MOD)):
+        print(f"[seg-rows] n={n} kind={kind} mode={mode} tune={tune}", flush=True)
+        ok, oi, ss, fl = P.segmented_partition(torch.from_numpy(x).to(DEV), st, pred, mode=mode, tune=tune)
+        torch.cuda.synchronize()
+        assert P.segmented_error() == 0
+        ys, idx, seg, flags = O.partition2L_rows(x, shape, kind, 3, s_rows, mode)
+        assert np.array_equal(oi.cpu().numpy().astype(np.int64), idx)
+        assert np.array_equal(ss.cpu().numpy(), seg) and np.array_equal(fl.cpu().numpy(), flags)
+        nout = n if mode == 0 else int(seg.sum())
+        assert np.array_equal(ok.cpu().numpy()[:nout].view(np.uint32), ys[:nout].view(np.uint32))
+
+
+def test_row_predicates_rejected_without_rows():
+    x = torch.zeros(16, dtype=torch.float32, device=DEV)
+    with pytest.raises(ValueError):
+        P.partition(x, P.Pred.lt_rows(torch.zeros(1, device=DEV)))

@@ -1,0 +1,48 @@
+"""mkII and mkSgmDescr (Section 2.1 segment helpers) as device outputs,
+bit-exact against the CPU oracle (itself pinned to the paper's worked
+examples)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+import paper_2506_23058_amd as P  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def _both(shape):
+    shape = np.asarray(shape, dtype=np.int64)
+    n = int(shape.sum())
+    print(f"[shape-tools] m={len(shape)} n={n}", flush=True)
+    st = torch.from_numpy(shape).to(DEV)
+    xs = np.arange(1, len(shape) + 1, dtype=np.int64) * 7 - 3
+    for dt in (torch.int32, torch.int64):
+        ii = P.mk_ii(st, n, dt)
+        assert np.array_equal(ii.cpu().numpy().astype(np.int64), O.mk_ii(shape))
+    d = P.mk_sgm_descr(st, torch.from_numpy(xs).to(DEV), n)
+    assert np.array_equal(d.cpu().numpy(), O.mk_sgm_descr(shape, xs))
+    assert P.shape_tools_error() == 0
+
+
+def test_paper_example_shape():
+    _both([0, 2, 1, 0, 3])
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_random_shapes(seed):
+    for m, med, sig, empty in [(1, 3, 0, 0), (500, 4, 2, 0.4), (10_000, 12, 1.5, 0.1), (3000, 1, 1, 0.5)]:
+        _both(W.segment_sizes(m, 300 + seed, median_log2=med, sigma_log2=sig, empty_frac=empty))
+
+
+def test_degenerate_and_bad_shapes():
+    _both([])
+    _both([0, 0])
+    _both([70_001, 0, 130_003])
+    st = torch.tensor([3, -1, 4], dtype=torch.int64, device=DEV)
+    out = P.mk_ii(st, 6)
+    assert P.shape_tools_error() == P._lib.IXP_EINVAL
