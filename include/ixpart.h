@@ -295,7 +295,7 @@ enum { IXP_MONO_LE = 0, IXP_MONO_LT = 1, IXP_MONO_GE = 2, IXP_MONO_GT = 3 };
  *          kept elements); 16 Y[Z[i]] != X[i] bitwise.  first_violation = the
  *          least index failing one of 2..16, n if only 1 fails.
  * Intervals are half-open.  Inj and Bij need a workspace of about 4.25 bytes
- * per value of Rcd [lo,hi) (two bitmaps and a first-index table), plus 8
+ * per value of Rcd [lo,hi) (two bitmaps and a first-index table), plus 4
  * bytes per element when n >= 2^16; Rcd may span at most 2^36 values. */
 typedef struct {
     int32_t holds;

@@ -63,7 +63,7 @@ struct PropsArgs {
     unsigned long long *bucket_total;   // [nbuckets]
     unsigned long long *bucket_start;   // [nbuckets]
     unsigned long long *wg_base;        // [gridDim of pass 1][nbuckets]
-    unsigned long long *records;        // [entries inside Rcd]
+    uint32_t *records;                  // [entries inside Rcd] value - lo - bucket base (20 bits)
     // FiltPart
     const uint32_t *fp_src;
     const uint32_t *fp_dst;
@@ -323,11 +323,12 @@ template <bool X64, int UNROLL>
 __global__ __launch_bounds__(kPropsBlock) void props_place_kernel(PropsArgs a) {
     constexpr int kPer = X64 ? 2 : 4;
     constexpr int kRound = kPropsBlock * UNROLL * kPer;   // records per round at most
+    static_assert(kRound <= (1 << 14), "rank field");
     extern __shared__ unsigned long long base[];          // [nb] global write position
     const int nb = a.nbuckets;
     uint32_t *rhist = reinterpret_cast<uint32_t *>(base + nb);   // [nb] round counts
     uint32_t *roff = rhist + nb;                                 // [nb] round offsets
-    unsigned long long *stage = reinterpret_cast<unsigned long long *>(roff + nb);   // 8-aligned: 16 nb bytes in
+    uint32_t *stage = roff + nb;                                 // [kRound] staged records
     uint16_t *sbkt = reinterpret_cast<uint16_t *>(stage + kRound);
     __shared__ uint32_t wsum[kPropsBlock / 64];
     const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
@@ -341,10 +342,10 @@ __global__ __launch_bounds__(kPropsBlock) void props_place_kernel(PropsArgs a) {
     const int64_t g0 = static_cast<int64_t>(blockIdx.x) * blockDim.x + tid;
     const int64_t wg_g0 = static_cast<int64_t>(blockIdx.x) * blockDim.x;   // workgroup-uniform
     typedef uint32_t v4 __attribute__((ext_vector_type(4)));
+    constexpr uint32_t kOut = ~0u;   // not inside Rcd
     for (int64_t rb = 0; wg_g0 + rb < groups; rb += UNROLL * stride) {
-        unsigned long long rec[UNROLL * kPer];
-        int bk[UNROLL * kPer];
-        uint32_t rk[UNROLL * kPer];
+        uint32_t rec[UNROLL * kPer];    // offset inside the bucket
+        uint32_t meta[UNROLL * kPer];   // bucket << 14 | rank inside the round, or kOut
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) {
             const int64_t gi = g0 + rb + u * stride;
@@ -366,10 +367,9 @@ __global__ __launch_bounds__(kPropsBlock) void props_place_kernel(PropsArgs a) {
                 const int64_t v = val[q];
                 const bool in = gi < groups && a.lo <= v && v < a.hi;
                 const uint64_t o = static_cast<uint64_t>(v - a.lo);
-                bk[k] = in ? static_cast<int>(o >> kBucketShift) : -1;
-                rec[k] = (static_cast<unsigned long long>(gi * kPer + q) << kBucketShift) |
-                         (o & ((1ull << kBucketShift) - 1));
-                rk[k] = in ? atomicAdd(rhist + bk[k], 1u) : 0u;
+                const uint32_t bk = static_cast<uint32_t>(o >> kBucketShift);
+                rec[k] = static_cast<uint32_t>(o & ((1ull << kBucketShift) - 1));
+                meta[k] = in ? (bk << 14) | atomicAdd(rhist + bk, 1u) : kOut;
             }
         }
         __syncthreads();
@@ -400,10 +400,11 @@ __global__ __launch_bounds__(kPropsBlock) void props_place_kernel(PropsArgs a) {
         for (int w = 0; w < kPropsBlock / 64; ++w) round_total += wsum[w];
 #pragma unroll
         for (int k = 0; k < UNROLL * kPer; ++k) {
-            if (bk[k] >= 0) {
-                const uint32_t slot = roff[bk[k]] + rk[k];
+            if (meta[k] != kOut) {
+                const uint32_t bk = meta[k] >> 14;
+                const uint32_t slot = roff[bk] + (meta[k] & ((1u << 14) - 1));
                 stage[slot] = rec[k];
-                sbkt[slot] = static_cast<uint16_t>(bk[k]);
+                sbkt[slot] = static_cast<uint16_t>(bk);
             }
         }
         __syncthreads();
@@ -425,13 +426,14 @@ __global__ __launch_bounds__(kPropsBlock) void props_place_kernel(PropsArgs a) {
             if (!(a.lo <= v && v < a.hi)) continue;
             const uint64_t o = static_cast<uint64_t>(v - a.lo);
             const int b = static_cast<int>(o >> kBucketShift);
-            const unsigned long long rec = (static_cast<unsigned long long>(i) << kBucketShift) |
-                                           (o & ((1ull << kBucketShift) - 1));
-            a.records[base[b]] = rec;
+            a.records[base[b]] = static_cast<uint32_t>(o & ((1ull << kBucketShift) - 1));
             base[b] += 1;
         }
     }
 }
+
+// Records placed per workgroup and round: 32 per bucket for 256 buckets.
+constexpr int kPlaceRound = 8192;
 
 constexpr int kCheckThreads = 1024;
 constexpr int kBucketWords = (1 << kBucketShift) / 32;
@@ -445,8 +447,7 @@ __global__ __launch_bounds__(kCheckThreads) void props_check_kernel(PropsArgs a)
     const unsigned long long r0 = a.bucket_start[b], r1 = r0 + a.bucket_total[b];
     bool dup_seen = false;
     for (unsigned long long r = r0 + tid; r < r1; r += kCheckThreads) {
-        const unsigned long long rec = __builtin_nontemporal_load(a.records + r);
-        const uint32_t off = static_cast<uint32_t>(rec & ((1ull << kBucketShift) - 1));
+        const uint32_t off = __builtin_nontemporal_load(a.records + r);
         const uint32_t bit = 1u << (off & 31);
         const uint32_t old = atomicOr(bits + (off >> 5), bit);
         if (old & bit) {
@@ -822,7 +823,7 @@ size_t bucket_bytes(int64_t n, int nb) {
     if (!nb) return 0;
     return round_up(static_cast<size_t>(nb) * 8, 256) * 2 +
            round_up(static_cast<size_t>(kPass1Grid) * nb * 8, 256) +
-           round_up(static_cast<size_t>(n) * 8, 256);
+           round_up(static_cast<size_t>(n) * 4, 256);
 }
 
 int64_t rcd_width(int64_t n, uint32_t mask, const ixp_prop_args *a) {
@@ -914,7 +915,7 @@ extern "C" int ixp_check_props(const void *x, int32_t x_t, int64_t n, uint32_t m
         a.bucket_total = reinterpret_cast<unsigned long long *>(bp);
         a.bucket_start = reinterpret_cast<unsigned long long *>(bp + bb);
         a.wg_base = reinterpret_cast<unsigned long long *>(bp + 2 * bb);
-        a.records = reinterpret_cast<unsigned long long *>(
+        a.records = reinterpret_cast<uint32_t *>(
             bp + 2 * bb + round_up(static_cast<size_t>(kPass1Grid) * a.nbuckets * 8, 256));
     }
     a.fp_src = static_cast<const uint32_t *>(pa->fp_src);
@@ -940,13 +941,14 @@ extern "C" int ixp_check_props(const void *x, int32_t x_t, int64_t n, uint32_t m
             IXP_LAUNCH("props_pass1", (props_pass1_kernel<false, 4>), dim3(grid), dim3(kPropsBlock), hist_lds, st, b);
         if (b.bucketed) {
             IXP_LAUNCH("props_bucket_scan", props_bucket_scan_kernel, dim3(1), dim3(1024), 0, st, b);
-            // base[nb] + round counts/offsets [2 nb] (+pad) + staged records and bucket ids
-            const size_t place_lds = static_cast<size_t>(b.nbuckets) * 16 +
-                                     static_cast<size_t>(kPropsBlock * 4 * (b.x64 ? 2 : 4)) * 10;
+            // base[nb] + round counts/offsets [2 nb] + staged records (4 B) and bucket ids (2 B)
+            const size_t place_lds = static_cast<size_t>(b.nbuckets) * 16 + static_cast<size_t>(kPlaceRound) * 6;
             if (b.x64)
-                IXP_LAUNCH("props_place", (props_place_kernel<true, 4>), dim3(grid), dim3(kPropsBlock), place_lds, st, b);
+                IXP_LAUNCH("props_place", (props_place_kernel<true, kPlaceRound / (kPropsBlock * 2)>), dim3(grid),
+                           dim3(kPropsBlock), place_lds, st, b);
             else
-                IXP_LAUNCH("props_place", (props_place_kernel<false, 4>), dim3(grid), dim3(kPropsBlock), place_lds, st, b);
+                IXP_LAUNCH("props_place", (props_place_kernel<false, kPlaceRound / (kPropsBlock * 4)>), dim3(grid),
+                           dim3(kPropsBlock), place_lds, st, b);
             IXP_LAUNCH("props_check", props_check_kernel, dim3(b.nbuckets), dim3(kCheckThreads), 0, st, b);
         }
         if (main_mask & (IXP_INJ | IXP_BIJ)) {
