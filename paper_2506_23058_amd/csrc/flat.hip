@@ -53,6 +53,9 @@ constexpr size_t kWsHeader = 256;   // ticket (u32), error word (i32), padding
 #ifndef IXP_VEC_RUNS
 #define IXP_VEC_RUNS 1
 #endif
+#ifndef IXP_XCD_MAP
+#define IXP_XCD_MAP 1
+#endif
 
 template <int MODE, int VEC>
 struct FlatCfg {
@@ -186,7 +189,18 @@ __global__ __launch_bounds__((FlatCfg<MODE, VEC>::kBlock)) void flat_scan_kernel
     const int lane = tid & (kWave - 1);
     int64_t t;
     if (MODE == IXP_MODE_PARTITION) {
+#if IXP_XCD_MAP
+        // workgroups are dealt round-robin to the 8 XCDs; give each XCD a
+        // contiguous range of tiles, so neighbouring output runs (and the
+        // partial lines between them) meet in one L2
+        const int64_t nt = a.num_tiles;
+        const int64_t per = (nt + 7) / 8;
+        const int64_t x = blockIdx.x % 8, k = blockIdx.x / 8;
+        const int64_t full = nt - (per - 1) * 8;   // XCDs that get `per` tiles (the rest get per - 1)
+        t = x < full ? x * per + k : full * per + (x - full) * (per - 1) + k;
+#else
         t = blockIdx.x;
+#endif
     } else {
         if (tid == 0) sh[0] = atomicAdd(a.ticket, 1u);
         __syncthreads();
