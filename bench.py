@@ -85,7 +85,7 @@ def main():
                     help="also run one plain device copy of the input (counter calibration)")
     ap.add_argument("--section", default=None,
                     help="run only this section (segmented, autograd, props, verify, pairs, "
-                         "partition3) and print it")
+                         "partition3, shape_tools) and print it")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -103,7 +103,7 @@ def main():
     if args.section:
         fn = {"segmented": section_segmented, "autograd": section_autograd,
               "props": section_props, "verify": section_verify, "pairs": section_pairs,
-              "partition3": section_partition3}[args.section]
+              "partition3": section_partition3, "shape_tools": section_shape_tools}[args.section]
         print(json.dumps({args.section: fn(args, torch, np, P, W, dev)}))
         return
     n = W.FLAT_LARGE_N
@@ -220,6 +220,7 @@ def sections(args, torch, np, P, W, dev, x, out_keys, out_idx, split):
     res["scatter_verification_partition2"] = section_verify(args, torch, np, P, W, dev)
     res["get_smallest_pairs"] = section_pairs(args, torch, np, P, W, dev)
     res["partition3_2^28_f32"] = section_partition3(args, torch, np, P, W, dev, x)
+    res["shape_tools"] = section_shape_tools(args, torch, np, P, W, dev)
     return res
 
 
@@ -481,6 +482,30 @@ def section_partition3(args, torch, np, P, W, dev, x=None):
     sc = k.get("flatv_scatter", {}).get("avg_ms", 0.0)
     return {"ms": t * 1e3, "GElem_s": n / t / 1e9, "counts": cnt.cpu().tolist(),
             "scatter_alg_GBps": 12 * n / (sc * 1e-3) / 1e9 if sc else None, "kernels": k}
+
+
+def section_shape_tools(args, torch, np, P, W, dev):
+    """mkII and mkSgmDescr of the 10^4-row shape (7.04e7 elements, int32 row
+    numbers) and sgmSum of 2^26 int64 values with a flag at every row start
+    of the same kind of shape."""
+    shape = W.segment_sizes(W.SEG_M, W.SEG_SIZES_SEED)
+    n = int(shape.sum())
+    st = torch.from_numpy(shape).to(dev)
+    steps = max(3, args.steps // 2)
+    ii = torch.empty(n, dtype=torch.int32, device=dev)
+    t_ii = timed(lambda: P.mk_ii(st, n, torch.int32), steps, 2, torch)
+    xs_rows = torch.arange(1, W.SEG_M + 1, dtype=torch.int64, device=dev)
+    t_descr = timed(lambda: P.mk_sgm_descr(st, xs_rows, n), steps, 2, torch)
+    del ii
+    m = 1 << 26
+    flags = torch.zeros(m, dtype=torch.uint8, device=dev)
+    flags[torch.from_numpy(np.unique(np.random.default_rng(W.SEG_KEYS_SEED).integers(0, m, m >> 12))).to(dev)] = 1
+    xs = torch.from_numpy(W.int_keys(m, W.SEG_KEYS_SEED).astype(np.int64)).to(dev)
+    out = torch.empty_like(xs)
+    t_sg = timed(lambda: P.sgm_sum(flags, xs, out), steps, 2, torch)
+    return {"mk_ii_int32": {"n": n, "ms": t_ii * 1e3, "alg_GBps": 4 * n / t_ii / 1e9},
+            "mk_sgm_descr_int64": {"n": n, "ms": t_descr * 1e3, "alg_GBps": 8 * n / t_descr / 1e9},
+            "sgm_sum_2^26_int64": {"ms": t_sg * 1e3, "alg_GBps": 17 * m / t_sg / 1e9}}
 
 
 def cpu_baseline(W, np):

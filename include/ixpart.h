@@ -215,6 +215,16 @@ int ixp_mk_sgm_descr(const int64_t *d_shape, int64_t m, int64_t n,
                      const int64_t *d_xs, int64_t *d_out, void *ws,
                      size_t ws_bytes, void *stream);
 
+/* sgmSum (Section 2.1, figure "Running Examples", right): d_out[i] = the
+ * inclusive scan of d_xs under (fx, vx) (+) (fy, vy) = (fx || fy, fy ? vy :
+ * vx + vy), i.e. the sum of d_xs over [last j <= i with d_flags[j] != 0, i]
+ * (from 0 if no such j).  int64 values (wrapping on overflow), u8 flags.
+ * Workspace: ixp_sgm_sum_workspace(n) bytes, 8-byte aligned.  Single pass
+ * with a decoupled look-back; 2 kernels. */
+size_t ixp_sgm_sum_workspace(int64_t n);
+int ixp_sgm_sum(const uint8_t *d_flags, const int64_t *d_xs, int64_t n,
+                int64_t *d_out, void *ws, size_t ws_bytes, void *stream);
+
 /* Blocking: times every candidate tiling on the given arguments (which it
  * overwrites) and stores the fastest in *best (and its time in *best_ms). */
 int ixp_tune_segmented(const void *keys, int32_t key_t, int64_t n,

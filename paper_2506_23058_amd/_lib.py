@@ -72,6 +72,8 @@ SIGNATURES = {
     "ixp_partition": (ctypes.c_int, [_P, _I32, _I64, _PP, _I32, _P, _P, _I32, _P, _P, _SZ, _P]),
     "ixp_partition_v_workspace": (_SZ, [_I64]),
     "ixp_mk_ii_workspace": (_SZ, [_I64, _I64]),
+    "ixp_sgm_sum_workspace": (_SZ, [_I64]),
+    "ixp_sgm_sum": (ctypes.c_int, [_P, _P, _I64, _P, _P, _SZ, _P]),
     "ixp_mk_ii": (ctypes.c_int, [_P, _I64, _I64, _P, _I32, _P, _SZ, _P]),
     "ixp_mk_sgm_descr": (ctypes.c_int, [_P, _I64, _I64, _P, _P, _P, _SZ, _P]),
     "ixp_partition_v": (ctypes.c_int, [_P, _I32, _I64, _PC, _P, _P, _I32, _P, _P, _SZ, _P]),

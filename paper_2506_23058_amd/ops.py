@@ -277,6 +277,22 @@ def mk_sgm_descr(shape: torch.Tensor, xs: torch.Tensor, n: int, ws_tag: str = "s
     return out
 
 
+def sgm_sum(flags: torch.Tensor, xs: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """sgmSum: running int64 sums of xs that restart at every nonzero flag."""
+    _check_dev(flags, xs)
+    flags = flags.contiguous().view(torch.uint8) if flags.dtype == torch.bool else flags.contiguous()
+    xs = xs.contiguous()
+    if xs.dtype != torch.int64 or flags.dtype != torch.uint8 or flags.numel() != xs.numel():
+        raise ValueError("sgm_sum needs uint8/bool flags and int64 values of one length")
+    n = xs.numel()
+    if out is None:
+        out = torch.empty_like(xs)
+    ws = workspace(L.lib().ixp_sgm_sum_workspace(n), xs.device, "sgm_sum")
+    rc = L.lib().ixp_sgm_sum(_ptr(flags), _ptr(xs), n, _ptr(out), _ptr(ws), ws.numel(), _stream_ptr(xs.device))
+    L.check(rc, "ixp_sgm_sum")
+    return out
+
+
 def shape_tools_error(ws_tag: str = "shape_tools", device="cuda:0") -> int:
     """Blocking: the error recorded by the last mk_ii / mk_sgm_descr call."""
     ws = _ws_cache.get((str(torch.device(device)), ws_tag))

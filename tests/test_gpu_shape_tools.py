@@ -46,3 +46,27 @@ def test_degenerate_and_bad_shapes():
     st = torch.tensor([3, -1, 4], dtype=torch.int64, device=DEV)
     out = P.mk_ii(st, 6)
     assert P.shape_tools_error() == P._lib.IXP_EINVAL
+
+
+@pytest.mark.parametrize("n", [0, 1, 7, 8191, 8192, 8193, 100_003, (1 << 22) + 5])
+@pytest.mark.parametrize("density", [0.0, 1e-5, 0.01, 0.5, 1.0])
+def test_sgm_sum_matches_oracle(n, density):
+    g = np.random.default_rng(n + int(density * 1000))
+    flags = (g.random(n) < density).astype(np.uint8)
+    xs = g.integers(-2**40, 2**40, n)
+    print(f"[sgm_sum] n={n} density={density}", flush=True)
+    got = P.sgm_sum(torch.from_numpy(flags).to(DEV), torch.from_numpy(xs).to(DEV))
+    assert np.array_equal(got.cpu().numpy(), O.sgm_sum(flags, xs))
+
+
+def test_sgm_sum_builds_mk_ii():
+    """mkII as the paper builds it: sgmSum over the segment descriptor of the
+    row numbers (row k at o_k, 0 elsewhere; flags where it is nonzero)."""
+    shape = W.segment_sizes(5000, 120, median_log2=8, sigma_log2=2.0, empty_frac=0.2)
+    n = int(shape.sum())
+    st = torch.from_numpy(shape).to(DEV)
+    rows = torch.arange(1, len(shape) + 1, dtype=torch.int64, device=DEV)   # k + 1
+    descr = P.mk_sgm_descr(st, rows, n)
+    vals = torch.where(descr > 0, descr - 1, torch.zeros_like(descr))
+    ii = P.sgm_sum((descr > 0).to(torch.uint8), vals)
+    assert torch.equal(ii, P.mk_ii(st, n)) and np.array_equal(ii.cpu().numpy(), O.mk_ii(shape))
