@@ -34,7 +34,8 @@
 namespace ixp {
 namespace {
 
-constexpr size_t kSegHeader = 256;   // error i32 @4, item count i64 @8
+constexpr size_t kSegHeader = 256;   // error i32 @4, item count i64 @8, scan ticket u32 @16
+constexpr int64_t kScanChunk = 8192;  // item counts per workgroup of seg_scan_items
 
 // Per-item descriptor written by seg_items and completed by seg_item_bases.
 struct alignas(16) SegItem {
@@ -61,6 +62,8 @@ struct SegArgs {
     SegItem *items;       // [max_items]
     int64_t *prefix;      // [max_items + 1] exclusive scan of item counts
     unsigned long long *counts;   // [max_items] trues per counted item
+    uint64_t *scan_desc;          // [ceil(max_items / kScanChunk)] look-back descriptors
+    uint32_t *scan_ticket;
     int64_t max_items;
     int32_t *err;
     int64_t *num_items;
@@ -172,6 +175,12 @@ __global__ __launch_bounds__(kSetupThreads) void seg_setup_kernel(SegArgs a) {
 __global__ __launch_bounds__(256) void seg_items_kernel(SegArgs a) {
     __shared__ int64_t s_off[257], s_it[257];
     if (*a.err != 0) return;
+    {   // clear the item scan's ticket and look-back descriptors
+        const int64_t g = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+        const int64_t nd = (a.max_items + kScanChunk - 1) / kScanChunk;
+        for (int64_t j = g; j < nd; j += static_cast<int64_t>(gridDim.x) * 256) a.scan_desc[j] = 0;
+        if (g == 0) *a.scan_ticket = 0;
+    }
     const int64_t r0 = static_cast<int64_t>(blockIdx.x) * 256;
     const int nr = static_cast<int>(a.m - r0 < 256 ? a.m - r0 : 256);
     for (int j = threadIdx.x; j <= nr; j += blockDim.x) {
@@ -234,33 +243,53 @@ __global__ __launch_bounds__(256) void seg_count_kernel(SegArgs a, Pred pred) {
 }
 
 // ------------------------------------------------------------------- scan --
-// One workgroup scans all item counts (chunks of 1024 * 8 items) into
-// prefix[0..num_items]; items of rows counted in place (partition, one item)
-// count 0.
+// Exclusive scan of the item counts into prefix[0..num_items]; items of rows
+// counted in place (partition, one item) count 0.  Workgroups take chunks of
+// 8192 counts in ticket order, scan them (8 per thread, wave shuffles, LDS)
+// and chain the chunks with a decoupled look-back.
 __global__ __launch_bounds__(1024) void seg_scan_items_kernel(SegArgs a) {
     __shared__ int64_t lds[16];
+    __shared__ int64_t sh[2];
+    constexpr int kPer = kScanChunk / 1024;
+    const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
     const int64_t nitems = *a.num_items;
-    constexpr int kPer = 8;
-    int64_t carry = 0;
-    for (int64_t c0 = 0; c0 < nitems; c0 += 1024 * kPer) {
-        const int64_t i0 = c0 + static_cast<int64_t>(threadIdx.x) * kPer;
-        int64_t v[kPer];
-        int64_t sum = 0;
-#pragma unroll
-        for (int j = 0; j < kPer; ++j) {
-            v[j] = i0 + j < nitems ? static_cast<int64_t>(a.counts[i0 + j]) : 0;
-            sum += v[j];
-        }
-        int64_t tot;
-        int64_t acc = carry + block_exclusive_scan_1024(sum, lds, &tot);
-#pragma unroll
-        for (int j = 0; j < kPer; ++j) {
-            if (i0 + j < nitems) a.prefix[i0 + j] = acc;
-            acc += v[j];
-        }
-        carry += tot;
+    const int64_t nchunks = (nitems + kScanChunk - 1) / kScanChunk;
+    if (tid == 0) sh[0] = atomicAdd(a.scan_ticket, 1u);
+    __syncthreads();
+    const int64_t c = sh[0];
+    if (nitems == 0) {
+        if (c == 0 && tid == 0) a.prefix[0] = 0;
+        return;
     }
-    if (threadIdx.x == 0) a.prefix[nitems] = carry;
+    if (c >= nchunks) return;
+    const int64_t i0 = c * kScanChunk + static_cast<int64_t>(tid) * kPer;
+    int64_t v[kPer];
+    int64_t sum = 0;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        v[j] = i0 + j < nitems ? static_cast<int64_t>(a.counts[i0 + j]) : 0;
+        sum += v[j];
+    }
+    int64_t tot;
+    const int64_t in_chunk = block_exclusive_scan_1024(sum, lds, &tot);
+    if (wave == 0) {
+        // a chunk holds at most 8192 * 16384 trues: below 2^32, as the
+        // look-back's aggregates must be
+        if (lane == 0 && c > 0) desc_store(a.scan_desc + c, kStA | static_cast<uint64_t>(tot));
+        const int64_t e = c == 0 ? 0 : lookback<4>(a.scan_desc, c, 0, a.err);
+        if (lane == 0) {
+            desc_store(a.scan_desc + c, kStP | static_cast<uint64_t>(e + tot));
+            sh[1] = e;
+            if (c == nchunks - 1) a.prefix[nitems] = e + tot;
+        }
+    }
+    __syncthreads();
+    int64_t acc = sh[1] + in_chunk;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        if (i0 + j < nitems) a.prefix[i0 + j] = acc;
+        acc += v[j];
+    }
 }
 
 // One thread per item: output bases from the prefix.  Partition: a row of
@@ -521,7 +550,9 @@ int launch_all(const SegArgs &a, const Pred &p, const SegGeom &g, int mode, int 
                                 ? ceil_div(chunk_waves, 4) : static_cast<int64_t>(cus) * 64;
     IXP_LAUNCH("seg_count", (seg_count_kernel<Pred>), dim3(static_cast<uint32_t>(cblocks)), dim3(256), 0,
                st, a, p);
-    IXP_LAUNCH("seg_scan_items", seg_scan_items_kernel, dim3(1), dim3(1024), 0, st, a);
+    IXP_LAUNCH("seg_scan_items", seg_scan_items_kernel,
+               dim3(static_cast<uint32_t>(ceil_div(a.max_items > 0 ? a.max_items : 1, kScanChunk))), dim3(1024), 0,
+               st, a);
     const uint32_t iblocks = static_cast<uint32_t>(ceil_div(a.max_items, 256));
     IXP_LAUNCH("seg_item_bases", seg_item_bases_kernel, dim3(iblocks), dim3(256), 0, st, a);
     if (launch_status() != IXP_OK) return IXP_EHIP;
@@ -532,7 +563,8 @@ size_t seg_workspace(int64_t n, int64_t m, const SegGeom &g) {
     const int64_t mi = seg_max_items(n, m, g.tile());
     return kSegHeader + round_up(static_cast<size_t>(m + 1) * 8, 256) * 2 +
            round_up(static_cast<size_t>(mi) * sizeof(SegItem), 256) +
-           round_up(static_cast<size_t>(mi + 1) * 8, 256) + static_cast<size_t>(mi) * 8;
+           round_up(static_cast<size_t>(mi + 1) * 8, 256) + round_up(static_cast<size_t>(mi) * 8, 256) +
+           static_cast<size_t>(ceil_div(mi > 0 ? mi : 1, kScanChunk)) * 8;
 }
 
 void set_layout(int64_t n, int64_t m, const int64_t *d_shape, const SegGeom &g, void *ws, SegArgs *a);
@@ -596,6 +628,9 @@ void set_layout(int64_t n, int64_t m, const int64_t *d_shape, const SegGeom &g, 
         w + kSegHeader + 2 * rows_bytes + round_up(static_cast<size_t>(a->max_items) * sizeof(SegItem), 256));
     a->counts = reinterpret_cast<unsigned long long *>(
         reinterpret_cast<char *>(a->prefix) + round_up(static_cast<size_t>(a->max_items + 1) * 8, 256));
+    a->scan_desc = reinterpret_cast<uint64_t *>(reinterpret_cast<char *>(a->counts) +
+                                                round_up(static_cast<size_t>(a->max_items) * 8, 256));
+    a->scan_ticket = reinterpret_cast<uint32_t *>(w + 16);
     a->tile = g.tile();
     a->tile_shift = 0;
     while ((int64_t{1} << a->tile_shift) < a->tile) ++a->tile_shift;
