@@ -56,6 +56,10 @@ constexpr size_t kWsHeader = 256;   // ticket (u32), error word (i32), padding
 #ifndef IXP_XCD_MAP
 #define IXP_XCD_MAP 1
 #endif
+// rows of 64 x 4 elements a counting wave loads at once
+#ifndef IXP_COUNT_ROWS
+#define IXP_COUNT_ROWS 16
+#endif
 
 template <int MODE, int VEC>
 struct FlatCfg {
@@ -96,13 +100,14 @@ __global__ void flat_init_kernel(uint32_t *ticket, int32_t *err, uint64_t *desc,
 }
 
 // Counting: wave w owns the contiguous tiles [w*k, w*k + k) (k =
-// tiles_per_wave).  It counts them in order, 1024 elements at a time, writes
+// tiles_per_wave).  It counts them in order, a whole 4096-element tile at a
+// time (16 vector loads in flight per lane), writes
 // each tile's exclusive prefix inside the run to desc[t] and the run total to
 // wsum[w].
 template <int VEC, class Pred>
 __global__ __launch_bounds__(256) void flat_count_kernel(FlatArgs a, Pred pred) {
     constexpr int kTile = FlatCfg<IXP_MODE_PARTITION, VEC>::kTile;
-    using WT = Tile<kWave, (VEC == 4 ? 4 : 16), VEC>;
+    using WT = Tile<kWave, (VEC == 4 ? IXP_COUNT_ROWS : 16), VEC>;
     constexpr int kChunks = kTile / WT::kSize;
     static_assert(kChunks * WT::kSize == kTile, "count chunks");
     const int lane = threadIdx.x & (kWave - 1);

@@ -268,7 +268,7 @@ struct VArgs {
 template <int V, class Cls>
 __global__ __launch_bounds__(256) void flatv_count_kernel(VArgs a, Cls cl) {
     constexpr int kTile = kVBlockThreads * kVRows * 4;
-    using WT = TileV<kWave, 4, V>;   // one wave, 1024 elements
+    using WT = TileV<kWave, 8, V>;   // one wave, 2048 elements: 8 vector loads in flight per lane
     constexpr int kChunks = kTile / WT::kSize;
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t w = static_cast<int64_t>(blockIdx.x) * (256 / kWave) + wave_id();

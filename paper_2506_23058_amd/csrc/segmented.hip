@@ -36,6 +36,10 @@ namespace {
 
 constexpr size_t kSegHeader = 256;   // error i32 @4, item count i64 @8, scan ticket u32 @16
 constexpr int64_t kScanChunk = 8192;  // item counts per workgroup of seg_scan_items
+#ifndef IXP_SEG_COUNT_ROWS
+#define IXP_SEG_COUNT_ROWS 4
+#endif
+constexpr int kSegCountLog = IXP_SEG_COUNT_ROWS == 16 ? 12 : IXP_SEG_COUNT_ROWS == 8 ? 11 : 10;   // log2(256 * rows)
 
 // Per-item descriptor written by seg_items and completed by seg_item_bases.
 struct alignas(16) SegItem {
@@ -222,10 +226,11 @@ __global__ __launch_bounds__(256) void seg_items_kernel(SegArgs a) {
 // at most tile/1024 times, so the atomics do not queue.
 template <class Pred>
 __global__ __launch_bounds__(256) void seg_count_kernel(SegArgs a, Pred pred) {
-    using WT = Tile<kWave, 4, 4>;   // one wave, 1024 elements
+    using WT = Tile<kWave, IXP_SEG_COUNT_ROWS, 4>;   // one wave, 256 * rows elements
+    constexpr int kCLog = kSegCountLog;
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t nitems = *a.num_items;
-    const int cshift = a.tile_shift - 10;   // chunks per item = tile / 1024
+    const int cshift = a.tile_shift > kCLog ? a.tile_shift - kCLog : 0;   // log2(chunks per item)
     const int64_t work = nitems << cshift;
     const int64_t nw = static_cast<int64_t>(gridDim.x) * 4;
     for (int64_t w = static_cast<int64_t>(blockIdx.x) * 4 + wave_id(); w < work; w += nw) {
@@ -233,7 +238,7 @@ __global__ __launch_bounds__(256) void seg_count_kernel(SegArgs a, Pred pred) {
         const int64_t c = w & ((int64_t{1} << cshift) - 1);
         const SegItem &d = a.items[it];
         if (a.mode == IXP_MODE_PARTITION && (d.kind & 1)) continue;   // counted in place
-        const int64_t b = d.base + (c << 10);
+        const int64_t b = d.base + (c << kCLog);
         if (b >= d.hi) continue;
         WT chunk;
         chunk.load(a.keys, a.n, b, d.lo, d.hi, pred.at_row(d.row), !Pred::kUsesFlags, 0, lane);
@@ -545,7 +550,7 @@ int launch_all(const SegArgs &a, const Pred &p, const SegGeom &g, int mode, int 
     if (launch_status() != IXP_OK) return IXP_EHIP;
     const int cus = device_cus();
     // one wave per chunk of the largest possible item list, capped
-    const int64_t chunk_waves = a.max_items * (a.tile >> 10);
+    const int64_t chunk_waves = a.max_items * (a.tile > (1 << kSegCountLog) ? a.tile >> kSegCountLog : 1);
     const int64_t cblocks = ceil_div(chunk_waves, 4) < static_cast<int64_t>(cus) * 64
                                 ? ceil_div(chunk_waves, 4) : static_cast<int64_t>(cus) * 64;
     IXP_LAUNCH("seg_count", (seg_count_kernel<Pred>), dim3(static_cast<uint32_t>(cblocks)), dim3(256), 0,
