@@ -72,3 +72,48 @@ def test_product_path_fails_loudly_without_library(monkeypatch, tmp_path):
     with pytest.raises(RuntimeError, match="missing"):
         L.lib()
     importlib.reload(L)
+
+
+def test_new_entry_points_validate_on_the_host():
+    """Argument errors of the entry points added for the evaluation's
+    comparison and the next-stage programs are caught before any launch."""
+    import paper_2506_23058_amd._lib as L
+    lib = L.lib()
+    # reduce-by-index, checked scatter, zero fill, keep flags
+    assert lib.ixp_hist_min(None, -1, 0, None, L.I64, None, 0, None) == L.IXP_EINVAL
+    assert lib.ixp_hist_min(None, 4, 0, None, 7, None, 0, None) == L.IXP_EINVAL
+    assert lib.ixp_scatter_checked_workspace(-1) == 0
+    assert lib.ixp_scatter_checked_workspace(1000) >= 8000
+    assert lib.ixp_scatter_checked(None, 10, None, L.I64, None, 5, 3, None, None, 0, None) == L.IXP_EINVAL
+    verdict = ctypes.create_string_buffer(64)   # host memory: the call must fail before using it
+    assert lib.ixp_scatter_checked(None, 10, None, L.I64, None, 0, 16, verdict, None, 0, None) == L.IXP_EUNSUPPORTED
+    assert lib.ixp_zero(None, 16, None) == L.IXP_EINVAL
+    assert lib.ixp_zero(None, 0, None) == L.IXP_OK
+    assert lib.ixp_match_min(None, None, 4, None, L.I64, None, 3, None) == L.IXP_EINVAL
+    # v-way partition: class count, unsorted thresholds, key type
+    assert lib.ixp_partition_v_workspace(-1) == 0
+    # structs of the handle's own argument types (an earlier test reloads the module)
+    c = lib.ixp_partition_v.argtypes[3]._type_()
+    c.kind, c.v = L.CLASS_THRESH, 5
+    cnt = ctypes.c_int64(0)
+    ws = ctypes.create_string_buffer(1 << 16)
+    args = (ctypes.byref(c), None, None, L.I32, ctypes.addressof(cnt), ws, len(ws), None)
+    assert lib.ixp_partition_v(None, L.F32, 0, *args) == L.IXP_EINVAL         # v > 4
+    c.v, c.s[0], c.s[1] = 3, 0.5, 0.2
+    assert lib.ixp_partition_v(None, L.F32, 0, *args) == L.IXP_EINVAL         # thresholds not sorted
+    c.kind, c.v = L.CLASS_MOD, 3
+    assert lib.ixp_partition_v(None, L.F32, 0, *args) == L.IXP_EINVAL         # modulus needs int32 keys
+    # segment tools and sgmSum
+    assert lib.ixp_mk_ii_workspace(-1, 3) == 0
+    assert lib.ixp_mk_ii(None, 3, 10, None, L.I32, None, 0, None) == L.IXP_EINVAL
+    assert lib.ixp_mk_ii(None, 0, 0, None, 9, None, 0, None) == L.IXP_EINVAL
+    assert lib.ixp_mk_sgm_descr(None, 2, 5, None, None, None, 0, None) == L.IXP_EINVAL
+    assert lib.ixp_sgm_sum_workspace(-1) == 0
+    assert lib.ixp_sgm_sum(None, None, 10, None, None, 0, None) == L.IXP_EINVAL
+    # row predicates are rejected by calls without rows
+    p = lib.ixp_partition.argtypes[3]._type_()
+    p.kind = L.PRED_LT_ROW
+    split = ctypes.c_int64(0)
+    rc = lib.ixp_partition(None, L.F32, 0, ctypes.byref(p), 0, None, None, L.I64,
+                           ctypes.addressof(split), ws, len(ws), None)
+    assert rc == L.IXP_EINVAL
