@@ -219,8 +219,8 @@ int ixp_mk_sgm_descr(const int64_t *d_shape, int64_t m, int64_t n,
  * inclusive scan of d_xs under (fx, vx) (+) (fy, vy) = (fx || fy, fy ? vy :
  * vx + vy), i.e. the sum of d_xs over [last j <= i with d_flags[j] != 0, i]
  * (from 0 if no such j).  int64 values (wrapping on overflow), u8 flags.
- * Workspace: ixp_sgm_sum_workspace(n) bytes, 8-byte aligned.  Single pass
- * with a decoupled look-back; 2 kernels. */
+ * Workspace: ixp_sgm_sum_workspace(n) bytes, 8-byte aligned.  3 kernels
+ * (chunk aggregates, their scan, a rescan of each chunk). */
 size_t ixp_sgm_sum_workspace(int64_t n);
 int ixp_sgm_sum(const uint8_t *d_flags, const int64_t *d_xs, int64_t n,
                 int64_t *d_out, void *ws, size_t ws_bytes, void *stream);
