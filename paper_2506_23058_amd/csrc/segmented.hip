@@ -694,7 +694,7 @@ extern "C" int ixp_tune_segmented(const void *keys, int32_t key_t, int64_t n,
     if (!best) return IXP_EINVAL;
     if (reps < 1) reps = 1;
     hipStream_t st = as_stream(stream);
-    static const int kCands[][2] = {{256, 4}, {256, 8}, {512, 2}, {512, 4}, {512, 8},
+    static const int kCands[][2] = {{256, 2}, {256, 4}, {256, 8}, {512, 2}, {512, 4}, {512, 8},
                                     {1024, 2}, {1024, 4}};
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return IXP_EHIP;
@@ -703,14 +703,15 @@ extern "C" int ixp_tune_segmented(const void *keys, int32_t key_t, int64_t n,
     int rc_out = IXP_EUNSUPPORTED;
     for (const auto &c : kCands) {
         // persistent grids (as many workgroups per CU as fit, or one fewer),
-        // and oversubscribed grids of 16 or 64 per CU, where most workgroups
-        // take a single item and the hardware overlaps them
-        for (int wpc = 0; wpc < 4; ++wpc) {
+        // and oversubscribed grids of 16, 32 or 64 per CU, where most
+        // workgroups take a single item and the hardware overlaps them
+        for (int wpc = 0; wpc < 5; ++wpc) {
             ixp_tuning t{c[0], c[1], 0, 0};
             SegGeom g = geom_from(&t);
             if (wpc == 1) g.wgs_per_cu = g.wgs_per_cu > 1 ? g.wgs_per_cu - 1 : 1;
             if (wpc == 2) g.wgs_per_cu = 16;
             if (wpc == 3) g.wgs_per_cu = 64;
+            if (wpc == 4) g.wgs_per_cu = 32;
             t.wgs_per_cu = g.wgs_per_cu;
             SegArgs a;
             HostPred hp;
