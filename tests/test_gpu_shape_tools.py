@@ -70,3 +70,15 @@ def test_sgm_sum_builds_mk_ii():
     vals = torch.where(descr > 0, descr - 1, torch.zeros_like(descr))
     ii = P.sgm_sum((descr > 0).to(torch.uint8), vals)
     assert torch.equal(ii, P.mk_ii(st, n)) and np.array_equal(ii.cpu().numpy(), O.mk_ii(shape))
+
+
+def test_sgm_sum_chunks_of_several_tiles():
+    """Above 8192 * 8192 elements a chunk holds several tiles, rescanned in
+    order with a carried prefix."""
+    n = (1 << 26) + 12_345
+    g = np.random.default_rng(121)
+    flags = (g.random(n) < 2e-6).astype(np.uint8)     # long stretches without a flag
+    xs = g.integers(-2**30, 2**30, n)
+    print(f"[sgm_sum] n={n} multi-tile chunks", flush=True)
+    got = P.sgm_sum(torch.from_numpy(flags).to(DEV), torch.from_numpy(xs).to(DEV))
+    assert np.array_equal(got.cpu().numpy(), O.sgm_sum(flags, xs))
