@@ -163,13 +163,26 @@ int ixp_partition_v(const void *keys, int32_t key_t, int64_t n,
  * each holding `rows` x 4 elements (rows in {2,4,8}, tile <= 16384); a tile
  * is block*rows*4 elements, and every row is cut into work items of at most
  * one tile.  `wgs_per_cu` (1..64, 0 = as many as fit) sizes the grid of the
- * main kernel: workgroup w takes items w, w + grid, w + 2*grid, ...  A NULL
- * tuning pointer selects the default (512 x 4, as many as fit). */
+ * main kernel: workgroup w takes items w, w + grid, w + 2*grid, ...
+ * `row_sync` says how, in PARTITION mode, a row of 2..256 items learns its
+ * true count T_k (rows of more items always take the counting pass):
+ *   IXP_ROW_SYNC_WAIT  (0) inside the main kernel: each item publishes its
+ *                      own count and waits, for a bounded number of polls,
+ *                      for those of the row's other items; an item still
+ *                      unpublished then is counted from its keys by the
+ *                      waiting workgroup, so the wait always ends and the
+ *                      result does not depend on timing;
+ *   IXP_ROW_SYNC_COUNT (1) a separate counting pass reads the row first;
+ *   IXP_ROW_SYNC_NOWAIT(2) as WAIT with no polling: every sibling not yet
+ *                      published is counted by the waiting workgroup (the
+ *                      fallback of WAIT, made the rule; for tests).
+ * A NULL tuning pointer selects the default (512 x 4, as many as fit, WAIT). */
+enum { IXP_ROW_SYNC_WAIT = 0, IXP_ROW_SYNC_COUNT = 1, IXP_ROW_SYNC_NOWAIT = 2 };
 typedef struct {
     int32_t block;
     int32_t rows;
     int32_t wgs_per_cu;
-    int32_t reserved;
+    int32_t row_sync;
 } ixp_tuning;
 
 size_t ixp_segmented_workspace(int64_t n, int64_t m, const ixp_tuning *tune);
@@ -189,8 +202,11 @@ size_t ixp_segmented_workspace(int64_t n, int64_t m, const ixp_tuning *tune);
  * A negative size or a size sum different from n is detected on the device:
  * the call then writes no output and ixp_read_error() on the same workspace
  * reports IXP_EINVAL.  Enqueues 6 kernels (shape scan, item records, counts
- * of rows spanning several items, item scan, item bases, main), all
- * stream-ordered with no host synchronisation: capturable into a HIP graph.
+ * of the multi-item rows that the main kernel does not synchronise itself,
+ * item scan, item bases, main), all stream-ordered with no host
+ * synchronisation: capturable into a HIP graph.  Under IXP_ROW_SYNC_WAIT the
+ * main kernel's workgroups wait on one another's published counts; the wait
+ * is bounded, so no workgroup depends on another being resident.
  * Alignment (else IXP_EINVAL): keys and ws 16 bytes, out_idx 4 indices,
  * out_keys, d_flags_out and a flag predicate's array 4 bytes. */
 int ixp_segmented_partition(const void *keys, int32_t key_t, int64_t n,
@@ -225,8 +241,9 @@ size_t ixp_sgm_sum_workspace(int64_t n);
 int ixp_sgm_sum(const uint8_t *d_flags, const int64_t *d_xs, int64_t n,
                 int64_t *d_out, void *ws, size_t ws_bytes, void *stream);
 
-/* Blocking: times every candidate tiling on the given arguments (which it
- * overwrites) and stores the fastest in *best (and its time in *best_ms). */
+/* Blocking: times every candidate tiling (tile shape, grid and, in PARTITION
+ * mode, row sync WAIT or COUNT) on the given arguments (which it overwrites)
+ * and stores the fastest in *best (and its time in *best_ms). */
 int ixp_tune_segmented(const void *keys, int32_t key_t, int64_t n,
                        const int64_t *d_shape, int64_t m, const ixp_pred *pred,
                        int32_t mode, void *out_keys, void *out_idx,

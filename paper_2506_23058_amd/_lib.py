@@ -20,6 +20,7 @@ MODE_PARTITION, MODE_FILTER = 0, 1
 RANGE, MONO, INJ, BIJ, FILTPART = 1, 2, 4, 8, 16
 CLASS_MOD, CLASS_THRESH, CLASS_BYTES = 0, 1, 2
 MONO_LE, MONO_LT, MONO_GE, MONO_GT = 0, 1, 2, 3
+ROW_SYNC_WAIT, ROW_SYNC_COUNT, ROW_SYNC_NOWAIT = 0, 1, 2
 
 
 class ixp_pred(ctypes.Structure):
@@ -35,7 +36,7 @@ class ixp_classes(ctypes.Structure):
 
 class ixp_tuning(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("rows", ctypes.c_int32),
-                ("wgs_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("wgs_per_cu", ctypes.c_int32), ("row_sync", ctypes.c_int32)]
 
 
 class ixp_kernel_stat(ctypes.Structure):

@@ -19,27 +19,38 @@
 //                and item offsets;
 //   seg_items -- item descriptors, written in parallel over items;
 //   seg_count -- one wave per 1024-element chunk counts the trues of the items
-//                whose row spans several items (partition) or of every item
-//                (filter) into a dense array of item counts;
+//                whose row spans several items and is not synchronised in
+//                seg_main (partition), or of every item (filter), into a
+//                dense array of item counts;
 //   seg_scan_items / seg_item_bases -- one scan of all item counts, then per
 //                item its output bases and T_k of its row;
 //   seg_main  -- persistent workgroups take items round-robin; each
 //                loads its item, ranks the trues by ballot/mbcnt, writes the
 //                indices and descriptor bytes in input order and the keys,
 //                staged in LDS, as two contiguous runs.  A row that fits one
-//                item is read once: its T_k comes from the item itself.
+//                item is read once: its T_k comes from the item itself.  A
+//                row of 2..kSibMax items is read once too (partition, row
+//                sync WAIT): its items publish their counts to one another
+//                while their keys stay in registers.
 #include "device.hpp"
 #include "host.hpp"
 
 namespace ixp {
 namespace {
 
-constexpr size_t kSegHeader = 256;   // error i32 @4, item count i64 @8, scan ticket u32 @16
+constexpr size_t kSegHeader = 256;   // error i32 @4, item count i64 @8, scan ticket u32 @16,
+                                     // counted items u64 @24
 constexpr int64_t kScanChunk = 8192;  // item counts per workgroup of seg_scan_items
 #ifndef IXP_SEG_COUNT_ROWS
 #define IXP_SEG_COUNT_ROWS 4
 #endif
 constexpr int kSegCountLog = IXP_SEG_COUNT_ROWS == 16 ? 12 : IXP_SEG_COUNT_ROWS == 8 ? 11 : 10;   // log2(256 * rows)
+// Rows of 2..kSibMax items exchange their counts inside seg_main.  A
+// published count is kCntReady | trues.  A waiting item polls at most
+// kSibPolls times before counting the rest itself.
+constexpr int kSibMax = 256;
+constexpr uint64_t kCntReady = kStA;
+constexpr uint32_t kSibPolls = 64;
 
 // Per-item descriptor written by seg_items and completed by seg_item_bases.
 struct alignas(16) SegItem {
@@ -48,8 +59,10 @@ struct alignas(16) SegItem {
     int64_t tbase;       // output position of the item's first true
     int64_t fbase;       // output position of the item's first false
     int32_t row;         // row k
-    int32_t kind;        // bit 0: row fits one item; bit 1: first item of its row
-    int64_t spare;       // pads the descriptor to six 8-byte words
+    int32_t kind;        // bit 0: row fits one item; bit 1: first item of its row;
+                         // bit 2: row synchronised in seg_main, with its item
+                         // count in bits 8..23 (tbase then holds o_k)
+    int64_t first;       // first item of the row (bit 2), else 0
 };
 
 struct SegArgs {
@@ -71,10 +84,12 @@ struct SegArgs {
     int64_t max_items;
     int32_t *err;
     int64_t *num_items;
+    unsigned long long *num_counted;   // items whose trues seg_count counts
     int64_t tile;
     int32_t tile_shift;   // tile = 2^tile_shift
     int32_t mode;
     int32_t need_keys;
+    int32_t row_sync;     // IXP_ROW_SYNC_*
 };
 
 int64_t seg_max_items(int64_t n, int64_t m, int64_t tile) {
@@ -116,7 +131,10 @@ __global__ __launch_bounds__(kSetupThreads) void seg_setup_kernel(SegArgs a) {
     __shared__ int64_t lds_a[16], lds_b[16];
     __shared__ int bad;
     const int tid = threadIdx.x;
-    if (tid == 0) bad = 0;
+    if (tid == 0) {
+        bad = 0;
+        *a.num_counted = 0;
+    }
     __syncthreads();
     int64_t carry_off = 0, carry_items = 0;
     for (int64_t c0 = 0; c0 < a.m; c0 += static_cast<int64_t>(kSetupThreads) * kSetupPer) {
@@ -178,7 +196,9 @@ __global__ __launch_bounds__(kSetupThreads) void seg_setup_kernel(SegArgs a) {
 // more than many rows of one item.  Empty rows get T_k = 0 here.
 __global__ __launch_bounds__(256) void seg_items_kernel(SegArgs a) {
     __shared__ int64_t s_off[257], s_it[257];
+    __shared__ unsigned long long s_counted;
     if (*a.err != 0) return;
+    if (threadIdx.x == 0) s_counted = 0;
     {   // clear the item scan's ticket and look-back descriptors
         const int64_t g = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
         const int64_t nd = (a.max_items + kScanChunk - 1) / kScanChunk;
@@ -205,18 +225,24 @@ __global__ __launch_bounds__(256) void seg_items_kernel(SegArgs a) {
         const int64_t i0 = s_it[lo], i1 = s_it[lo + 1];
         const int64_t q = idx - i0;
         const int64_t ak = o & ~int64_t{3};
+        const int64_t nit = i1 - i0;
+        const bool sib = a.mode == IXP_MODE_PARTITION && a.row_sync != IXP_ROW_SYNC_COUNT && nit > 1 &&
+                         nit <= kSibMax;
         SegItem d;
         d.base = ak + q * a.tile;
         d.lo = d.base > o ? d.base : o;
         d.hi = d.base + a.tile < e ? d.base + a.tile : e;
-        d.tbase = 0;
+        d.tbase = sib ? o : 0;
         d.fbase = 0;
         d.row = static_cast<int32_t>(r0 + lo);
-        d.kind = (i1 - i0 == 1 ? 1 : 0) | (q == 0 ? 2 : 0);
-        d.spare = 0;
+        d.kind = (nit == 1 ? 1 : 0) | (q == 0 ? 2 : 0) | (sib ? 4 | static_cast<int32_t>(nit << 8) : 0);
+        d.first = sib ? i0 : 0;
         a.items[idx] = d;
         a.counts[idx] = 0;
+        if (a.mode != IXP_MODE_PARTITION || (nit > 1 && !sib)) atomicAdd(&s_counted, 1ull);
     }
+    __syncthreads();
+    if (threadIdx.x == 0 && s_counted) atomicAdd(a.num_counted, s_counted);
 }
 
 // ------------------------------------------------------------------ count --
@@ -229,6 +255,7 @@ __global__ __launch_bounds__(256) void seg_count_kernel(SegArgs a, Pred pred) {
     using WT = Tile<kWave, IXP_SEG_COUNT_ROWS, 4>;   // one wave, 256 * rows elements
     constexpr int kCLog = kSegCountLog;
     const int lane = threadIdx.x & (kWave - 1);
+    if (*a.num_counted == 0) return;   // every item is counted in seg_main
     const int64_t nitems = *a.num_items;
     const int cshift = a.tile_shift > kCLog ? a.tile_shift - kCLog : 0;   // log2(chunks per item)
     const int64_t work = nitems << cshift;
@@ -237,7 +264,7 @@ __global__ __launch_bounds__(256) void seg_count_kernel(SegArgs a, Pred pred) {
         const int64_t it = w >> cshift;
         const int64_t c = w & ((int64_t{1} << cshift) - 1);
         const SegItem &d = a.items[it];
-        if (a.mode == IXP_MODE_PARTITION && (d.kind & 1)) continue;   // counted in place
+        if (a.mode == IXP_MODE_PARTITION && (d.kind & 5)) continue;   // counted in seg_main
         const int64_t b = d.base + (c << kCLog);
         if (b >= d.hi) continue;
         WT chunk;
@@ -257,6 +284,7 @@ __global__ __launch_bounds__(1024) void seg_scan_items_kernel(SegArgs a) {
     __shared__ int64_t sh[2];
     constexpr int kPer = kScanChunk / 1024;
     const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
+    if (*a.num_counted == 0) return;   // no item needs the prefix
     const int64_t nitems = *a.num_items;
     const int64_t nchunks = (nitems + kScanChunk - 1) / kScanChunk;
     if (tid == 0) sh[0] = atomicAdd(a.scan_ticket, 1u);
@@ -304,13 +332,14 @@ __global__ __launch_bounds__(1024) void seg_scan_items_kernel(SegArgs a) {
 // so the base is the global prefix; the first item writes the row's T_k.
 __global__ __launch_bounds__(256) void seg_item_bases_kernel(SegArgs a) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (*a.num_counted == 0) return;
     const int64_t nitems = *a.num_items;
     if (i >= nitems) return;
     const SegItem d = a.items[i];
     const int64_t k = d.row;
     const int64_t i0 = a.item_off[k], i1 = a.item_off[k + 1];
     if (a.mode == IXP_MODE_PARTITION) {
-        if (d.kind & 1) return;   // one-item row: finished by the main kernel
+        if (d.kind & 5) return;   // finished by the main kernel
         const int64_t ok = a.offsets[k];
         const int64_t p0 = a.prefix[i0];
         const int64_t before = a.prefix[i] - p0;
@@ -326,6 +355,70 @@ __global__ __launch_bounds__(256) void seg_item_bases_kernel(SegArgs a) {
 }
 
 // ------------------------------------------------------------------- main --
+// Count exchange of a row of 2..kSibMax items, run by one wave of the
+// workgroup that holds item `it` (true count `tcount`): publishes the count,
+// then reads the row's items' counts 64 at a time (lane j of chunk c reads
+// item first + 64c + j).  Unpublished ones are polled again, kSibPolls times
+// at most over the whole row; those still missing are counted from their
+// keys here.  Leaves in out[0] the trues of the row before item `it` and in
+// out[1] the row's total T_k.  Every count is exact whoever computes it, so
+// the result does not depend on which items published in time.
+template <class Pred>
+__device__ __forceinline__ void row_counts(const SegArgs &a, const Pred &pred, int64_t it,
+                                           const SegItem &d, uint32_t tcount, int lane,
+                                           uint32_t *out) {
+    uint64_t *cnt = reinterpret_cast<uint64_t *>(a.counts);
+    const int nsib = (d.kind >> 8) & 0xffff;
+    const int me = static_cast<int>(it - d.first);
+    const bool nowait = a.row_sync == IXP_ROW_SYNC_NOWAIT;
+    if (lane == 0) desc_store(cnt + it, kCntReady | tcount);
+    uint32_t polls = kSibPolls;
+    uint32_t before = 0, total = 0;
+    for (int c0 = 0; c0 < nsib; c0 += kWave) {
+        const int j = c0 + lane;
+        const bool mine = j < nsib;
+        uint64_t w = j == me ? (kCntReady | tcount) : 0;
+        if (!nowait && mine && j != me) w = desc_load(cnt + d.first + j);
+        uint64_t missing = ballot(mine && !(w & kCntReady));
+        while (missing && !nowait && polls > 0) {
+            --polls;
+            __builtin_amdgcn_s_sleep(1);
+            if ((missing >> lane) & 1ull) w = desc_load(cnt + d.first + j);
+            missing = ballot(mine && !(w & kCntReady));
+        }
+        while (missing) {
+            // a plain strided loop: few registers are free while the tile is held
+            const int b = __builtin_ctzll(missing);
+            missing &= missing - 1;
+            const auto p = pred.at_row(d.row);
+            const SegItem &s = a.items[d.first + c0 + b];
+            const int64_t shi = s.hi;
+            uint32_t c = 0;
+            for (int64_t q0 = s.lo; q0 < shi; q0 += 4 * kWave) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int64_t q = q0 + u * kWave + lane;
+                    if (q < shi) {
+                        const uint32_t key = Pred::kUsesFlags ? 0u : a.keys[q];
+                        uint8_t f = 0;
+                        if constexpr (Pred::kUsesFlags) f = p.flags[q];
+                        c += p(key, f) ? 1u : 0u;
+                    }
+                }
+            }
+            c = wave_sum_u32(c);
+            if (lane == b) w = kCntReady | c;
+        }
+        const uint32_t v = mine ? static_cast<uint32_t>(w & kValMask) : 0u;
+        before += wave_sum_u32(j < me ? v : 0u);
+        total += wave_sum_u32(v);
+    }
+    if (lane == 0) {
+        out[0] = before;
+        out[1] = total;
+    }
+}
+
 // Persistent workgroups take items round-robin (item = blockIdx.x + k *
 // gridDim.x: no shared queue counter, whose serialised atomics would cost
 // ~10 ns per item).  Wave 0 prefetches the next item's 48-byte descriptor,
@@ -340,6 +433,7 @@ __global__ __launch_bounds__(BLOCK) void seg_main_kernel(SegArgs a, Pred pred) {
     __shared__ uint32_t wtot[T::kWaves];
     __shared__ int64_t sh_desc[kWords];
     __shared__ int64_t sh_item;
+    __shared__ uint32_t sh_row[2];
 
     const int tid = threadIdx.x;
     const int wave = wave_id();
@@ -364,9 +458,15 @@ __global__ __launch_bounds__(BLOCK) void seg_main_kernel(SegArgs a, Pred pred) {
         if (it >= nitems) break;
         SegItem d;
         {
+            // the record is the same for every lane: keep it in scalar registers
             int64_t w[kWords];
 #pragma unroll
-            for (int k = 0; k < kWords; ++k) w[k] = sh_desc[k];
+            for (int k = 0; k < kWords; ++k) {
+                const uint64_t x = static_cast<uint64_t>(sh_desc[k]);
+                const uint32_t xl = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(x));
+                const uint32_t xh = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(x >> 32));
+                w[k] = static_cast<int64_t>((static_cast<uint64_t>(xh) << 32) | xl);
+            }
             __builtin_memcpy(&d, w, sizeof(SegItem));
         }
         if (wave == 0) {   // overlaps with this item
@@ -386,6 +486,14 @@ __global__ __launch_bounds__(BLOCK) void seg_main_kernel(SegArgs a, Pred pred) {
             tbase = lo;
             fbase = lo + tcount;
             if (tid == 0 && a.seg_split) a.seg_split[d.row] = tcount;
+        }
+        if (MODE == IXP_MODE_PARTITION && (d.kind & 4)) {
+            if (wave == 0) row_counts(a, pred, it, d, tcount, lane, sh_row);
+            __syncthreads();
+            const int64_t ok = d.tbase, before = sh_row[0], tk = sh_row[1];
+            tbase = ok + before;
+            fbase = ok + tk + (lo - ok - before);
+            if (tid == 0 && (d.kind & 2) && a.seg_split) a.seg_split[d.row] = tk;
         }
         const bool first = (d.kind & 2) != 0;
 
@@ -475,7 +583,7 @@ int launch_tool(const SegArgs &a, Out *out, const int64_t *xs, hipStream_t st) {
 
 // ----------------------------------------------------------------- launch --
 struct SegGeom {
-    int block, rows, wgs_per_cu;
+    int block, rows, wgs_per_cu, row_sync;
     int64_t tile() const { return static_cast<int64_t>(block) * rows * 4; }
 };
 
@@ -483,15 +591,17 @@ struct SegGeom {
 bool geom_supported(const SegGeom &g) {
     const bool b = g.block == 256 || g.block == 512 || g.block == 1024;
     const bool r = g.rows == 2 || g.rows == 4 || g.rows == 8;
-    return b && r && g.tile() <= 16384 && g.wgs_per_cu >= 1 && g.wgs_per_cu <= 64;
+    return b && r && g.tile() <= 16384 && g.wgs_per_cu >= 1 && g.wgs_per_cu <= 64 &&
+           g.row_sync >= IXP_ROW_SYNC_WAIT && g.row_sync <= IXP_ROW_SYNC_NOWAIT;
 }
 
 SegGeom geom_from(const ixp_tuning *t) {
-    SegGeom g{512, 4, 3};
+    SegGeom g{512, 4, 3, IXP_ROW_SYNC_WAIT};
     if (t) {
         if (t->block) g.block = t->block;
         if (t->rows) g.rows = t->rows;
         g.wgs_per_cu = t->wgs_per_cu > 0 ? t->wgs_per_cu : 0;
+        g.row_sync = t->row_sync;
     }
     if (g.wgs_per_cu == 0) {
         // as many workgroups per CU as the LDS tile and 32 waves allow, at most 8
@@ -607,6 +717,7 @@ int prepare(const void *keys, int32_t key_t, int64_t n, const int64_t *d_shape, 
     a->flags_out = d_flags_out;
     a->mode = mode;
     a->need_keys = need_keys ? 1 : 0;
+    a->row_sync = g.row_sync;
     return IXP_OK;
 }
 
@@ -625,6 +736,7 @@ void set_layout(int64_t n, int64_t m, const int64_t *d_shape, const SegGeom &g, 
     a->flags_out = nullptr;
     a->err = reinterpret_cast<int32_t *>(w + 4);
     a->num_items = reinterpret_cast<int64_t *>(w + 8);
+    a->num_counted = reinterpret_cast<unsigned long long *>(w + 24);
     a->offsets = reinterpret_cast<int64_t *>(w + kSegHeader);
     a->item_off = reinterpret_cast<int64_t *>(w + kSegHeader + rows_bytes);
     a->items = reinterpret_cast<SegItem *>(w + kSegHeader + 2 * rows_bytes);
@@ -641,6 +753,7 @@ void set_layout(int64_t n, int64_t m, const int64_t *d_shape, const SegGeom &g, 
     while ((int64_t{1} << a->tile_shift) < a->tile) ++a->tile_shift;
     a->mode = IXP_MODE_PARTITION;
     a->need_keys = 0;
+    a->row_sync = g.row_sync;
 }
 
 int run(const SegArgs &a, const HostPred &hp, const SegGeom &g, int mode, int idx_t, hipStream_t st) {
@@ -701,12 +814,15 @@ extern "C" int ixp_tune_segmented(const void *keys, int32_t key_t, int64_t n,
     if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return IXP_EHIP; }
     float best_t = -1.f;
     int rc_out = IXP_EUNSUPPORTED;
+    // row sync matters in partition mode only
+    const int nsync = mode == IXP_MODE_PARTITION ? 2 : 1;
+    for (int sync = 0; sync < nsync; ++sync)
     for (const auto &c : kCands) {
         // persistent grids (as many workgroups per CU as fit, or one fewer),
         // and oversubscribed grids of 16, 32 or 64 per CU, where most
         // workgroups take a single item and the hardware overlaps them
         for (int wpc = 0; wpc < 5; ++wpc) {
-            ixp_tuning t{c[0], c[1], 0, 0};
+            ixp_tuning t{c[0], c[1], 0, sync == 0 ? IXP_ROW_SYNC_WAIT : IXP_ROW_SYNC_COUNT};
             SegGeom g = geom_from(&t);
             if (wpc == 1) g.wgs_per_cu = g.wgs_per_cu > 1 ? g.wgs_per_cu - 1 : 1;
             if (wpc == 2) g.wgs_per_cu = 16;

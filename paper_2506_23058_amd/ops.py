@@ -203,7 +203,9 @@ def _tuning(tune):
     if tune is None:
         return None
     t = L.ixp_tuning()
-    t.block, t.rows, t.wgs_per_cu = int(tune[0]), int(tune[1]), int(tune[2]) if len(tune) > 2 else 0
+    t.block, t.rows = int(tune[0]), int(tune[1])
+    t.wgs_per_cu = int(tune[2]) if len(tune) > 2 else 0
+    t.row_sync = int(tune[3]) if len(tune) > 3 else L.ROW_SYNC_WAIT
     return t
 
 
@@ -228,7 +230,8 @@ def segmented_partition(keys: torch.Tensor, shape: torch.Tensor, pred: Pred,
     the jagged array whose row sizes are ``shape`` (int64, on the device).
 
     Returns (out_keys, out_idx, seg_split, flags).  ``tune`` is a
-    (block, rows[, wgs_per_cu]) tuple, or None for the library default.
+    (block, rows[, wgs_per_cu[, row_sync]]) tuple, or None for the library
+    default.
     """
     _check_dev(keys, shape)
     keys = keys.contiguous()
@@ -311,7 +314,7 @@ def segmented_error(ws_tag: str = "segmented", device="cuda:0") -> int:
 def tune_segmented(keys, shape, pred, mode=L.MODE_PARTITION, idx_dtype=torch.int32,
                    want_flags=True, reps: int = 5):
     """Blocking autotuner: times every supported tiling on these arguments and
-    returns ((block, rows, wgs_per_cu), milliseconds)."""
+    returns ((block, rows, wgs_per_cu, row_sync), milliseconds)."""
     keys = keys.contiguous()
     shape = shape.contiguous()
     out_keys, out_idx, seg_split, flags = _seg_outputs(keys, shape, idx_dtype, want_flags,
@@ -330,7 +333,7 @@ def tune_segmented(keys, shape, pred, mode=L.MODE_PARTITION, idx_dtype=torch.int
         _ptr(ws), ws.numel(), reps, ctypes.byref(best), ctypes.byref(ms),
         _stream_ptr(keys.device))
     L.check(rc, "ixp_tune_segmented")
-    return (best.block, best.rows, best.wgs_per_cu), ms.value
+    return (best.block, best.rows, best.wgs_per_cu, best.row_sync), ms.value
 
 
 class SegmentedGraph:
@@ -633,7 +636,7 @@ def autotuned_tiling(keys, shape, pred, mode=L.MODE_PARTITION, idx_dtype=torch.i
     import os
     arch = torch.cuda.get_device_properties(keys.device).gcnArchName.split(":")[0]
     n, m = keys.numel(), shape.numel()
-    key = "|".join([arch, str(keys.dtype), str(mode), str(idx_dtype), pred.kind.__str__(),
+    key = "|".join(["tiling+rowsync", arch, str(keys.dtype), str(mode), str(idx_dtype), pred.kind.__str__(),
                     f"n2^{int(math.log2(max(n, 1)))}", f"m2^{int(math.log2(max(m, 1)))}"])
     path = _tune_cache_path()
     cache = {}

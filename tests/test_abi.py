@@ -57,6 +57,11 @@ def test_host_side_validation_without_gpu():
     t = L.ixp_tuning()
     t.block, t.rows = 300, 4
     assert lib.ixp_segmented_workspace(1000, 10, ctypes.byref(t)) == 0
+    t.block, t.rows = 256, 4
+    for sync, ok in ((L.ROW_SYNC_WAIT, True), (L.ROW_SYNC_COUNT, True), (L.ROW_SYNC_NOWAIT, True),
+                     (3, False), (-1, False)):
+        t.row_sync = sync
+        assert (lib.ixp_segmented_workspace(1000, 10, ctypes.byref(t)) > 0) == ok
     a = L.ixp_prop_args()
     a.lo, a.hi = 0, 1 << 28
     assert lib.ixp_check_props_workspace(1 << 28, 4, ctypes.byref(a)) >= (1 << 28) // 8

@@ -112,6 +112,7 @@ def test_config_segmented_full_compare():
     shape = W.segment_sizes(W.SEG_M, W.SEG_SIZES_SEED)
     keys = W.int_keys(int(shape.sum()), W.SEG_KEYS_SEED)
     run_both(keys, shape)
+    run_both(keys, shape, tune=(256, 4, 64, 2))   # every sibling counted by the waiter
     shape_e = W.segment_sizes(W.SEG_M, W.SEG_SIZES_SEED, empty_frac=0.1)
     run_both(keys[: int(shape_e.sum())].copy(), shape_e, mode=0)
 
@@ -142,6 +143,7 @@ def test_autotuner_returns_a_valid_tiling():
     st = torch.from_numpy(shape).to(DEV)
     best, ms = P.tune_segmented(kt, st, P.Pred.mod_eq(3, 0), reps=2)
     assert best[0] in (256, 512, 1024) and best[1] in (2, 4, 8) and ms > 0
+    assert best[3] in (0, 1)
     run_both(keys, shape, tune=best)
 
 
@@ -166,17 +168,45 @@ def test_rows_on_tile_boundaries(tune):
              flags=(W.int_keys(int(shape.sum()), 80) % 3 == 0).astype(np.uint8))
 
 
+@pytest.mark.parametrize("row_sync", [0, 1, 2])
+@pytest.mark.parametrize("geom", [(256, 2, 0), (256, 2, 64), (1024, 4, 0)])
+def test_row_sync_modes(row_sync, geom):
+    """Rows of 2..256 items learn T_k inside the main kernel (WAIT), from the
+    counting pass (COUNT), or by counting every sibling not yet published
+    (NOWAIT: the fallback of WAIT made the rule).  With 2048-element tiles,
+    rows of 64/65 and 128/129 items straddle the 64-wide chunks of the
+    exchange, and rows of 256/257 items the limit between the exchange and
+    the counting pass."""
+    t = 2048
+    shape = np.array([3, 64 * t - 3, 64 * t, 1, 64 * t + 1, 2, t + 1, 0, 65 * t, 7, 2 * t,
+                      128 * t, 128 * t + 3, 256 * t - 4, 256 * t + 2, 257 * t,
+                      63 * t + 5, 5, 3 * t - 1], dtype=np.int64)
+    o = np.concatenate([[0], np.cumsum(shape)])[:-1]
+    items = np.where(shape > 0, ((o & 3) + shape + t - 1) // t, 0)
+    assert {64, 65, 128, 129, 256, 257} <= set(items.tolist())
+    keys = W.int_keys(int(shape.sum()), 91)
+    tune = geom + (row_sync,)
+    run_both(keys, shape, tune=tune)
+    run_both(keys, shape, mode=1, tune=tune)
+    run_both(W.f32_uniform(int(shape.sum()), 92), shape, kind="lt", s=0.6, tune=tune)
+    flags = (W.int_keys(int(shape.sum()), 93) % 7 == 0).astype(np.uint8)
+    run_both(keys, shape, kind="flags", flags=flags, tune=tune)
+    mix = W.segment_sizes(700, 94, median_log2=13, sigma_log2=1.5, empty_frac=0.1)
+    run_both(W.int_keys(int(mix.sum()), 95), mix, tune=tune)
+
+
 def test_rows_of_millions_of_elements_among_small_rows():
     """Rows spanning hundreds of tiles next to rows of a few elements."""
     shape = np.array([5, 3_000_001, 7, 0, 70_000, 2_500_000, 1], dtype=np.int64)
     keys = W.int_keys(int(shape.sum()), 81)
     run_both(keys, shape)
     run_both(keys, shape, tune=(1024, 4))
+    run_both(keys, shape, tune=(256, 2, 0, 2))
     run_both(keys, shape, mode=1)
 
 
 @pytest.mark.parametrize("mode", [0, 1])
-@pytest.mark.parametrize("tune", [None, (256, 2), (1024, 4)])
+@pytest.mark.parametrize("tune", [None, (256, 2), (1024, 4), (256, 2, 0, 2), (512, 4, 0, 1)])
 def test_predicates_of_the_row_number(mode, tune):
     """partition2L with predicates of the row number k: x < s[k] (per-row
     thresholds) and x mod 3 == k mod 3, against the row-predicate oracle."""
