@@ -66,13 +66,24 @@ struct ClassBytes {
     }
 };
 
+// a[c] for a class c < V, as a[0] plus the steps a[k] - a[k-1] of every
+// k <= c.  Compares and adds only: a chain of selects on c == k is turned by
+// the compiler into an indexed load from a per-lane scratch copy of a[].
 template <int V, class T>
-__device__ __forceinline__ T pick(const T (&a)[V], uint32_t c) {
-    T r = a[0];
+struct Picker {
+    T a0;
+    T step[V - 1];
+    __device__ __forceinline__ explicit Picker(const T (&a)[V]) : a0(a[0]) {
 #pragma unroll
-    for (int k = 1; k < V; ++k) r = c == static_cast<uint32_t>(k) ? a[k] : r;
-    return r;
-}
+        for (int k = 1; k < V; ++k) step[k - 1] = a[k] - a[k - 1];
+    }
+    __device__ __forceinline__ T operator()(uint32_t c) const {
+        T r = a0;
+#pragma unroll
+        for (int k = 1; k < V; ++k) r += c >= static_cast<uint32_t>(k) ? step[k - 1] : T{0};
+        return r;
+    }
+};
 
 // --------------------------------------------------------------------- tile --
 // Same element layout as the partition2 tile (wave w owns a contiguous run,
@@ -396,6 +407,8 @@ __global__ __launch_bounds__(kVBlockThreads) void flatv_scatter_kernel(VArgs a, 
     }
 
     Idx *out_idx = static_cast<Idx *>(a.out_idx);
+    const Picker<V, int64_t> dst_of(dst);
+    const Picker<V, uint32_t> sbase_of(sbase);
 #pragma unroll
     for (int r = 0; r < kVRows; ++r) {
         const int64_t p0 = T::pos(lo, wave, r, lane);
@@ -406,8 +419,8 @@ __global__ __launch_bounds__(kVBlockThreads) void flatv_scatter_kernel(VArgs a, 
             const uint32_t c = tile.cls(r, q);
             const bool ok = tile.valid(r, q);
             vm |= static_cast<uint32_t>(ok) << q;
-            v[q] = static_cast<Idx>(pick<V>(dst, c) + tile.rank[r][q]);
-            if (a.out_keys && ok) stage[pick<V>(sbase, c) + tile.rank[r][q]] = tile.key[r][q];
+            v[q] = static_cast<Idx>(dst_of(c) + tile.rank[r][q]);
+            if (a.out_keys && ok) stage[sbase_of(c) + tile.rank[r][q]] = tile.key[r][q];
         }
         if (out_idx && vm) store_idx_group<4, Idx>(out_idx, p0, v, vm);
     }
