@@ -263,15 +263,16 @@ def section_segmented(args, torch, np, P, W, dev):
     t_calls = timed(per_call, 2, 1, torch)
     g.close()
     # the same tiling with the other way of learning T_k of multi-item rows
-    row_sync = tiling[3] if len(tiling) > 3 else 0
-    other = tuple(tiling[:3]) + (1 - row_sync,)
+    row_sync = tiling[3] if len(tiling) > 3 else P._lib.ROW_SYNC_AUTO
+    other = tuple(tiling[:3]) + (P._lib.ROW_SYNC_COUNT if row_sync != P._lib.ROW_SYNC_COUNT
+                                 else P._lib.ROW_SYNC_WAIT,)
     g2 = P.SegmentedGraph(keys, shape, pred, tune=other)
     t_other = timed(g2.launch, steps, 2, torch)
     g2.close()
     alg = n * (4 + 4 + 4 + 1) + W.SEG_M * 16
     return {"n": n, "m": W.SEG_M, "tiling": {"block": tiling[0], "rows": tiling[1],
                                              "wgs_per_cu": tiling[2],
-                                             "row_sync": ["wait", "count"][row_sync]},
+                                             "row_sync": ["auto", "count", "nowait", "wait"][row_sync]},
             "graph_ms_other_row_sync": t_other * 1e3,
             "tuner_ms": tune_ms, "tiling_from_cache": cached,
             "graph_ms": t_graph * 1e3, "graph_GElem_s": n / t_graph / 1e9,

@@ -166,18 +166,23 @@ int ixp_partition_v(const void *keys, int32_t key_t, int64_t n,
  * main kernel: workgroup w takes items w, w + grid, w + 2*grid, ...
  * `row_sync` says how, in PARTITION mode, a row of 2..256 items learns its
  * true count T_k (rows of more items always take the counting pass):
- *   IXP_ROW_SYNC_WAIT  (0) inside the main kernel: each item publishes its
+ *   IXP_ROW_SYNC_WAIT  (3) inside the main kernel: each item publishes its
  *                      own count and waits, for a bounded number of polls,
  *                      for those of the row's other items; an item still
  *                      unpublished then is counted from its keys by the
  *                      waiting workgroup, so the wait always ends and the
- *                      result does not depend on timing;
+ *                      result does not depend on timing.  It pays when the
+ *                      grid is oversubscribed (the hardware then starts a
+ *                      row's items back to back); with persistent grids the
+ *                      workgroups drift apart and the waits grow;
  *   IXP_ROW_SYNC_COUNT (1) a separate counting pass reads the row first;
+ *   IXP_ROW_SYNC_AUTO  (0) WAIT with 16 or more workgroups per CU, else COUNT;
  *   IXP_ROW_SYNC_NOWAIT(2) as WAIT with no polling: every sibling not yet
  *                      published is counted by the waiting workgroup (the
  *                      fallback of WAIT, made the rule; for tests).
- * A NULL tuning pointer selects the default (512 x 4, as many as fit, WAIT). */
-enum { IXP_ROW_SYNC_WAIT = 0, IXP_ROW_SYNC_COUNT = 1, IXP_ROW_SYNC_NOWAIT = 2 };
+ * A NULL tuning pointer selects the default: 256 x 4, 64 workgroups per CU,
+ * AUTO. */
+enum { IXP_ROW_SYNC_AUTO = 0, IXP_ROW_SYNC_COUNT = 1, IXP_ROW_SYNC_NOWAIT = 2, IXP_ROW_SYNC_WAIT = 3 };
 typedef struct {
     int32_t block;
     int32_t rows;

@@ -20,7 +20,7 @@ MODE_PARTITION, MODE_FILTER = 0, 1
 RANGE, MONO, INJ, BIJ, FILTPART = 1, 2, 4, 8, 16
 CLASS_MOD, CLASS_THRESH, CLASS_BYTES = 0, 1, 2
 MONO_LE, MONO_LT, MONO_GE, MONO_GT = 0, 1, 2, 3
-ROW_SYNC_WAIT, ROW_SYNC_COUNT, ROW_SYNC_NOWAIT = 0, 1, 2
+ROW_SYNC_AUTO, ROW_SYNC_COUNT, ROW_SYNC_NOWAIT, ROW_SYNC_WAIT = 0, 1, 2, 3
 
 
 class ixp_pred(ctypes.Structure):

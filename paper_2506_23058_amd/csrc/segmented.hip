@@ -89,7 +89,7 @@ struct SegArgs {
     int32_t tile_shift;   // tile = 2^tile_shift
     int32_t mode;
     int32_t need_keys;
-    int32_t row_sync;     // IXP_ROW_SYNC_*
+    int32_t row_sync;     // IXP_ROW_SYNC_COUNT, _WAIT or _NOWAIT
 };
 
 int64_t seg_max_items(int64_t n, int64_t m, int64_t tile) {
@@ -592,11 +592,13 @@ bool geom_supported(const SegGeom &g) {
     const bool b = g.block == 256 || g.block == 512 || g.block == 1024;
     const bool r = g.rows == 2 || g.rows == 4 || g.rows == 8;
     return b && r && g.tile() <= 16384 && g.wgs_per_cu >= 1 && g.wgs_per_cu <= 64 &&
-           g.row_sync >= IXP_ROW_SYNC_WAIT && g.row_sync <= IXP_ROW_SYNC_NOWAIT;
+           (g.row_sync == IXP_ROW_SYNC_COUNT || g.row_sync == IXP_ROW_SYNC_NOWAIT ||
+            g.row_sync == IXP_ROW_SYNC_WAIT);
 }
 
 SegGeom geom_from(const ixp_tuning *t) {
-    SegGeom g{512, 4, 3, IXP_ROW_SYNC_WAIT};
+    // default: the tiling the autotuner picks for 10^4 log-normal rows
+    SegGeom g{256, 4, 64, IXP_ROW_SYNC_AUTO};
     if (t) {
         if (t->block) g.block = t->block;
         if (t->rows) g.rows = t->rows;
@@ -611,6 +613,9 @@ SegGeom geom_from(const ixp_tuning *t) {
         if (w > 8) w = 8;
         g.wgs_per_cu = static_cast<int>(w < 1 ? 1 : w);
     }
+    // the in-kernel count exchange pays when a row's items run at the same
+    // time, i.e. on oversubscribed grids that the hardware fills in order
+    if (g.row_sync == IXP_ROW_SYNC_AUTO) g.row_sync = g.wgs_per_cu >= 16 ? IXP_ROW_SYNC_WAIT : IXP_ROW_SYNC_COUNT;
     return g;
 }
 

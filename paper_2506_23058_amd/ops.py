@@ -205,7 +205,7 @@ def _tuning(tune):
     t = L.ixp_tuning()
     t.block, t.rows = int(tune[0]), int(tune[1])
     t.wgs_per_cu = int(tune[2]) if len(tune) > 2 else 0
-    t.row_sync = int(tune[3]) if len(tune) > 3 else L.ROW_SYNC_WAIT
+    t.row_sync = int(tune[3]) if len(tune) > 3 else L.ROW_SYNC_AUTO
     return t
 
 

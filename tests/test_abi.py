@@ -58,8 +58,8 @@ def test_host_side_validation_without_gpu():
     t.block, t.rows = 300, 4
     assert lib.ixp_segmented_workspace(1000, 10, ctypes.byref(t)) == 0
     t.block, t.rows = 256, 4
-    for sync, ok in ((L.ROW_SYNC_WAIT, True), (L.ROW_SYNC_COUNT, True), (L.ROW_SYNC_NOWAIT, True),
-                     (3, False), (-1, False)):
+    for sync, ok in ((L.ROW_SYNC_AUTO, True), (L.ROW_SYNC_COUNT, True), (L.ROW_SYNC_NOWAIT, True),
+                     (L.ROW_SYNC_WAIT, True), (4, False), (-1, False)):
         t.row_sync = sync
         assert (lib.ixp_segmented_workspace(1000, 10, ctypes.byref(t)) > 0) == ok
     a = L.ixp_prop_args()

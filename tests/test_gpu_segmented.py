@@ -143,7 +143,7 @@ def test_autotuner_returns_a_valid_tiling():
     st = torch.from_numpy(shape).to(DEV)
     best, ms = P.tune_segmented(kt, st, P.Pred.mod_eq(3, 0), reps=2)
     assert best[0] in (256, 512, 1024) and best[1] in (2, 4, 8) and ms > 0
-    assert best[3] in (0, 1)
+    assert best[3] in (P._lib.ROW_SYNC_COUNT, P._lib.ROW_SYNC_WAIT)
     run_both(keys, shape, tune=best)
 
 
@@ -168,12 +168,13 @@ def test_rows_on_tile_boundaries(tune):
              flags=(W.int_keys(int(shape.sum()), 80) % 3 == 0).astype(np.uint8))
 
 
-@pytest.mark.parametrize("row_sync", [0, 1, 2])
+@pytest.mark.parametrize("row_sync", [0, 1, 2, 3])
 @pytest.mark.parametrize("geom", [(256, 2, 0), (256, 2, 64), (1024, 4, 0)])
 def test_row_sync_modes(row_sync, geom):
-    """Rows of 2..256 items learn T_k inside the main kernel (WAIT), from the
-    counting pass (COUNT), or by counting every sibling not yet published
-    (NOWAIT: the fallback of WAIT made the rule).  With 2048-element tiles,
+    """Rows of 2..256 items learn T_k inside the main kernel (WAIT, 3), from
+    the counting pass (COUNT, 1), by counting every sibling not yet published
+    (NOWAIT, 2: the fallback of WAIT made the rule), or by the grid's choice
+    (AUTO, 0).  With 2048-element tiles,
     rows of 64/65 and 128/129 items straddle the 64-wide chunks of the
     exchange, and rows of 256/257 items the limit between the exchange and
     the counting pass."""
