@@ -375,8 +375,9 @@ int ixp_hist_min(int64_t *d_dst, int64_t n_dst, int64_t neutral,
                  int64_t m, void *stream);
 
 /* d_flags[k] := 1 if 0 <= idx[k] < n_hist and d_hist[idx[k]] == vals[k],
- * else 0, for k < m: the `map2 (\i j -> H[i] == j) es is` step of
- * get_smallest_pairs (Section 6), H being an ixp_hist_min result.  The flags
+ * else 0, for k < m: the step of get_smallest_pairs (Sections 5.4 and 6)
+ * that keeps an entry whose value is the minimum recorded at its endpoint,
+ * d_hist being an ixp_hist_min result.  The flags
  * feed a filter with IXP_PRED_FLAGS.  d_flags 4-byte aligned; int64 hist and
  * vals; idx of type idx_t.  1 kernel. */
 int ixp_match_min(uint8_t *d_flags, const int64_t *d_hist, int64_t n_hist,

@@ -34,7 +34,7 @@ enum { IXO_MODE_PARTITION = 0, IXO_MODE_FILTER = 1 };
 enum { IXO_MONO_LE = 0, IXO_MONO_LT = 1, IXO_MONO_GE = 2, IXO_MONO_GT = 3 };
 
 /* ------------------------------------------------------------------------ */
-/* The predicate p, applied by `map (\x -> p x) xs` (Section 2.1).          */
+/* The predicate p, applied to every element by a map (Section 2.1).       */
 /* MOD_EQ: floor-modulus of an integer key by d equals r (d > 0).  The paper */
 /* does not fix the sign convention of %; floor-mod (result in [0,d)) is    */
 /* the reading taken.  LT: f32 key < s, IEEE comparison (NaN gives false).  */
@@ -118,12 +118,10 @@ int ixo_gather(void *dst, const void *src, int64_t n_src, const int64_t *is,
 }
 
 /* Reduce-by-index with min (Futhark's `hist i64.min`, used by
- * get_smallest_pairs in Section 6 and, for the dynamic verification of
- * scatter, in the evaluation of Section 6):
- *   dst = replicate n_dst neutral
- *   for i in 0..m-1: if 0 <= is[i] < n_dst then
- *       dst[is[i]] := min dst[is[i]] vs[i]
- * vs == NULL stands for iota m (vs[i] = i). */
+ * get_smallest_pairs in Sections 5.4 and 6 and, for the dynamic verification of
+ * scatter, in the evaluation of Section 6).  Every location starts at
+ * `neutral`; then each i whose index is[i] lies in [0, n_dst) lowers
+ * dst[is[i]] to vs[i] when vs[i] is smaller.  vs == NULL means vs[i] = i. */
 int ixo_hist_min(int64_t *dst, int64_t n_dst, int64_t neutral, const int64_t *is,
                  const int64_t *vs, int64_t m) {
     if (n_dst < 0 || m < 0 || (n_dst > 0 && !dst) || (m > 0 && !is)) return -1;
@@ -137,13 +135,12 @@ int ixo_hist_min(int64_t *dst, int64_t n_dst, int64_t neutral, const int64_t *is
     return 0;
 }
 
-/* get_smallest_pairs (Section 6, maximal matching): given edge endpoints es
- * (Range es [0, n_verts) is a precondition) and injective edge ids `is`, keep
- * the entries whose id is the least id at their endpoint:
- *   H  = hist min (neutral n_es) over es with values is      [n_verts]
- *   cs = for each k: H[es[k]] == is[k]
- *   es' = filter cs es ; is' = filter cs is   (input order kept)
- * Entries with es[k] outside [0, n_verts) are not kept (reading: the
+/* get_smallest_pairs (Sections 5.4 and 6, maximal matching): given edge
+ * endpoints es (Range es [0, n_verts) is a precondition) and injective edge
+ * ids `is`, keep the entries whose id is the least id at their endpoint.  A
+ * reduce-by-index with min (neutral n_es) of the ids over the endpoints gives
+ * one minimum per vertex; entry k is kept when the minimum at es[k] is is[k];
+ * the kept endpoints and ids are then filtered out, in input order.  Entries with es[k] outside [0, n_verts) are not kept (reading: the
  * precondition makes them absent; here they are dropped).  Writes es', is'
  * (capacity m each) and their length to *count. */
 int ixo_get_smallest_pairs(int64_t n_verts, int64_t n_es, const int64_t *es, const int64_t *is,
@@ -169,14 +166,14 @@ int ixo_get_smallest_pairs(int64_t n_verts, int64_t n_es, const int64_t *es, con
 /* Dynamically verified scatter: the "Base" variant of the scatter in
  * partition2 in the evaluation of Section 6 (table "tab:eval", right),
  * which checks at run time that no location is written twice, with a
- * reduce-by-index of atomic minima.  Steps:
- *   dst = replicate n_dst 0
- *   win = hist min m (is) (iota m)       -- least i writing each location
- *   a write i is safe iff is[i] is out of bounds or win[is[i]] == i
- *   verdict: holds iff every write is safe; first_violation = the least
- *            unsafe i (the earliest second write to a location), aux = is[i]
- *   dst[v] = vs[win[v]] for every written location v (the least writer wins).
- * With an injective `is` this equals scatter (replicate n_dst 0) is vs. */
+ * reduce-by-index of atomic minima.  The output starts zeroed; a
+ * reduce-by-index with min over the write positions i records, for every
+ * location, the least i that writes it (its winner).  Write i is safe when
+ * is[i] is out of bounds or i is the winner of is[i].  The verdict holds when
+ * every write is safe; otherwise first_violation is the least unsafe i (the
+ * earliest second write to a location) and aux = is[i].  Every written
+ * location then takes its winner's value, so with injective indices the
+ * result is the plain scatter into a zeroed array. */
 int ixo_scatter_checked(void *dst, int64_t n_dst, const int64_t *is, const void *vs,
                         int64_t m, int64_t elem_bytes, int64_t *verdict) {
     if (n_dst < 0 || m < 0 || elem_bytes <= 0 || !verdict) return -1;
@@ -264,22 +261,20 @@ int ixo_partition_v(const void *xs, int64_t n, int32_t kind, int32_t v, const fl
 }
 
 /* ------------------------------------------------------------------------ */
-/* partition2 (Section 2.1, figure "Running Examples", left):               */
-/*   cs       = map p xs                                                    */
-/*   flagsT   = map (c -> c ? 1 : 0) cs                                     */
-/*   flagsF   = map (b -> 1 - b) flagsT                                     */
-/*   indicesT = scan (+) 0 flagsT                                           */
-/*   num_true = n > 0 ? indicesT[n-1] : 0                                   */
-/*   tmp      = scan (+) 0 flagsF                                           */
-/*   indicesF = map (t -> t + num_true) tmp                                 */
-/*   indices  = map3 (c t f -> c ? t-1 : f-1) cs indicesT indicesF          */
-/*   ys       = scatter (replicate n 0) indices xs                          */
+/* partition2 (Section 2.1, figure "Running Examples", left), step by step: */
+/* the predicate gives a boolean per element; two 0/1 arrays mark the       */
+/* trues and the falses; an inclusive +-scan of each counts, for every      */
+/* element, the members of its class up to and including it; the number of */
+/* trues is the last count of the first scan; a true goes to its count      */
+/* minus one, a false to the number of trues plus its count minus one; the  */
+/* elements are scattered to those positions in a zeroed array of length n. */
 /* returns (num_true, ys).  `indices` is also returned: it is the scatter   */
 /* array whose InvFiltPart property the paper proves.                       */
 /*                                                                          */
 /* FILTER mode is the paper's `filter` (FiltPart with p^f = p and no        */
-/* partitioning predicate): indices = c ? t-1 : -1, and the scatter target  */
-/* has length num_true; the -1 entries are out of bounds and ignored.       */
+/* partitioning predicate): a true goes to its count minus one, a false to  */
+/* -1; the scatter target has length num_true, and the -1 entries are out   */
+/* of bounds and ignored.                                                   */
 /* ------------------------------------------------------------------------ */
 static int partition2_from_cs(const void *xs, int64_t kb, int64_t n,
                               const uint8_t *cs, int mode, void *ys,
@@ -304,7 +299,7 @@ static int partition2_from_cs(const void *xs, int64_t kb, int64_t n,
         for (int64_t i = 0; i < n; i++) flagsF[i] = 1 - flagsT[i];
         scan_plus_i64(flagsF, n, tmp);
         free(flagsF); flagsF = NULL;
-        indicesF = tmp; /* indicesF = map (t -> t + num_true) tmp, in place */
+        indicesF = tmp; /* the false counts shifted by num_true, in place */
         tmp = NULL;
         for (int64_t i = 0; i < n; i++) indicesF[i] = indicesF[i] + num_true;
         for (int64_t i = 0; i < n; i++)
@@ -370,13 +365,11 @@ int ixo_sgm_sum(const uint8_t *flags, const int64_t *xs, int64_t n,
 }
 
 /* mkSgmDescr shape xs: flat array of length sum(shape) in which every
- * non-empty segment starts with xs[k] and is otherwise zero.  Steps:
- *   rot = map (i -> i == 0 ? 0 : shape[i-1]) (iota m)
- *   scn = scan (+) 0 rot                       (segment offsets)
- *   ind = map2 (s i -> s <= 0 ? -1 : i) shape scn
- *   len = m > 0 ? scn[m-1] + shape[m-1] : 0
- *   res = scatter (replicate len 0) ind xs
- * Empty segments scatter to -1, which scatter ignores.  `out` must hold
+ * non-empty segment starts with xs[k] and is otherwise zero.  The sizes are
+ * shifted right by one (0 in front) and +-scanned, which gives every row's
+ * offset; a non-empty row keeps its offset as target index and an empty row
+ * gets -1, which the scatter ignores; the length is the last offset plus the
+ * last size; xs is scattered by these indices into a zeroed array.  `out` must hold
  * sum(shape) entries; returns -1 if a size is negative. */
 int ixo_mk_sgm_descr(const int64_t *shape, int64_t m, const int64_t *xs,
                      int64_t *out, int64_t out_len) {
@@ -400,14 +393,14 @@ int ixo_mk_sgm_descr(const int64_t *shape, int64_t m, const int64_t *xs,
     return rc;
 }
 
-/* mkII shape: segment number of every flat element.  Steps:
- *   beg_vs  = map (i -> i + 1) (iota m)
- *   sct_vs1 = mkSgmDescr shape beg_vs
- *   sct_vs  = map (v -> v == 0 ? 0 : v - 1) sct_vs1
- *   flags   = map (f -> f > 0) sct_vs
- *   II      = sgmSum flags sct_vs
- * (The listing mixes the names sct_vs / scat_vs; one array is meant.)  The
- * worked example maps [0,2,1,0,3] to [1,1,2,4,4,4]. */
+/* mkII shape: segment number of every flat element.  The rows are numbered
+ * from one and mkSgmDescr places each number at its row's start (zero
+ * elsewhere); taking one off every non-zero entry leaves row k's number k at
+ * its start; the positive entries mark segment starts, and a segmented sum
+ * over those marks spreads each number across its row (row 0, whose start
+ * holds 0 and no mark, gets the 0 that the sum carries from the array start).
+ * (The figure uses two spellings for one of these arrays; one array is
+ * meant.)  The worked example maps [0,2,1,0,3] to [1,1,2,4,4,4]. */
 int ixo_mk_ii(const int64_t *shape, int64_t m, int64_t *out, int64_t out_len) {
     if (m < 0) return -1;
     int64_t *beg_vs = malloc((size_t)(m > 0 ? m : 1) * sizeof(int64_t));

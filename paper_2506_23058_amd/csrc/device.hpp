@@ -1,10 +1,10 @@
 // device.hpp -- gfx950 device primitives shared by the partition kernels.
 //
 // Wave64 building blocks (ballot / mbcnt ranks, DPP reductions), the
-// predicates p of `cs = map p xs` (Section 2.1), the tile loader, the in-tile
-// rank computation, and the decoupled look-back over tile descriptors that
-// turns per-tile true counts into exclusive prefixes (the `scan (+) 0 flagsT`
-// of partition2, Section 2.1).
+// predicates p that partition2 maps over the elements (Section 2.1), the
+// tile loader, the in-tile rank computation, and the decoupled look-back over
+// tile descriptors that turns per-tile true counts into exclusive prefixes
+// (partition2's scan of the true flags, Section 2.1).
 #pragma once
 
 #include <hip/hip_runtime.h>

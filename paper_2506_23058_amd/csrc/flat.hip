@@ -1,9 +1,9 @@
 // flat.hip -- flat stable partition (partition2) and filter on gfx950.
 //
-// partition2 (Section 2.1, figure "Running Examples") computes
-//   cs = map p xs; indicesT = scan (+) 0 flagsT; num_true = last of indicesT;
-//   indicesF = num_true + scan (+) 0 flagsF; indices = c ? t-1 : f-1;
-//   ys = scatter zeros indices xs.
+// partition2 (Section 2.1, figure "Running Examples") evaluates the
+// predicate on every element, counts trues and falses with two inclusive
+// scans, sends a true to its true count minus one and a false to the number
+// of trues plus its false count minus one, and scatters the elements there.
 // Here the two scans collapse into one exclusive count of trues E(i), since
 // #falses before i = i - E(i); the index map becomes
 //   idx[i] = c_i ? E(i) : T + i - E(i)            (T = num_true)

@@ -62,9 +62,10 @@ __global__ __launch_bounds__(kVBlock) void hist_min_kernel(int64_t *dst, int64_t
     }
 }
 
-// flags[k] = (0 <= idx[k] < n_hist) && hist[idx[k]] == vals[k]: the
-// `map2 (\i j -> H[i] == j) es is` of get_smallest_pairs.  Four entries per
-// thread, their flags leave as one 32-bit store.
+// flags[k] = (0 <= idx[k] < n_hist) && hist[idx[k]] == vals[k]: the keep
+// flags of get_smallest_pairs (an entry whose value is the minimum recorded
+// at its endpoint).  Four entries per thread, their flags leave as one
+// 32-bit store.
 template <class Idx>
 __global__ __launch_bounds__(kVBlock) void match_min_kernel(uint8_t *flags, const int64_t *hist, int64_t n_hist,
                                                             const Idx *idx, const int64_t *vals, int64_t m) {

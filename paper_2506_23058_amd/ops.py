@@ -537,7 +537,7 @@ def match_min(hist: torch.Tensor, idx: torch.Tensor, vals: torch.Tensor,
 
 
 class SmallestPairs:
-    """get_smallest_pairs (Section 6, maximal matching) on the device, with
+    """get_smallest_pairs (Sections 5.4 and 6, maximal matching) on the device, with
     buffers kept across calls: H = hist min over es with values is, keep
     entry k iff H[es[k]] == is[k], and filter es and is by the kept flags
     (positions from a filter over the flags, then two 8-byte scatters).
