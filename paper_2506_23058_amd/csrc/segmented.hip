@@ -551,20 +551,32 @@ __global__ __launch_bounds__(BLOCK) void seg_main_kernel(SegArgs a, Pred pred) {
 //   mkII:       ii[i] = k for o_k <= i < o_k + s_k;
 //   mkSgmDescr: out[o_k] = xs[k] for every non-empty row k, 0 elsewhere.
 // Workgroup w takes items w, w + grid, ...; consecutive threads write
-// consecutive elements.
+// consecutive 16-byte groups of the item's aligned middle (when `out` is
+// 16-byte aligned), and single elements at its ends.
 template <int TOOL, class Out>
 __global__ __launch_bounds__(256) void seg_fill_kernel(SegArgs a, Out *out, const int64_t *xs) {
+    constexpr int kV = 16 / sizeof(Out);   // elements per 16-byte group
+    typedef Out vec_t __attribute__((ext_vector_type(kV)));
     if (*a.err != 0) return;
     const int64_t nitems = *a.num_items;
+    const bool vec_ok = (reinterpret_cast<uintptr_t>(out) & 15) == 0;
     for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
         const SegItem d = a.items[it];
         const bool first = (d.kind & 2) != 0;
-        const Out head = TOOL == 0 ? static_cast<Out>(d.row) : static_cast<Out>(first ? xs[d.row] : 0);
-        for (int64_t i = d.lo + threadIdx.x; i < d.hi; i += 256) {
-            Out v;
-            if (TOOL == 0) v = static_cast<Out>(d.row);
-            else v = i == d.lo ? head : static_cast<Out>(0);
-            stream_store(out + i, v);
+        const Out fill = TOOL == 0 ? static_cast<Out>(d.row) : static_cast<Out>(0);
+        const Out head = TOOL == 0 ? fill : static_cast<Out>(first ? xs[d.row] : 0);
+        // [v0, v1): whole groups; the rest element by element
+        int64_t v0 = (d.lo + kV - 1) / kV * kV, v1 = d.hi / kV * kV;
+        if (!vec_ok || v0 >= v1) v0 = v1 = d.hi;
+        for (int64_t i = d.lo + threadIdx.x; i < v0; i += 256) stream_store(out + i, i == d.lo ? head : fill);
+        for (int64_t i = v1 + threadIdx.x; i < d.hi; i += 256) stream_store(out + i, i == d.lo ? head : fill);
+        vec_t fv;
+#pragma unroll
+        for (int q = 0; q < kV; ++q) fv[q] = fill;
+        for (int64_t g = v0 / kV + threadIdx.x; g < v1 / kV; g += 256) {
+            vec_t v = fv;
+            if (TOOL == 1 && g * kV == d.lo) v[0] = head;
+            stream_store(reinterpret_cast<vec_t *>(out) + g, v);
         }
     }
 }

@@ -253,12 +253,21 @@ def segmented_partition(keys: torch.Tensor, shape: torch.Tensor, pred: Pred,
     return out_keys, out_idx, seg_split, flags
 
 
-def mk_ii(shape: torch.Tensor, n: int, out_dtype=torch.int64, ws_tag: str = "shape_tools") -> torch.Tensor:
+def _tool_out(out, n, dtype, device):
+    if out is None:
+        return torch.empty(n, dtype=dtype, device=device)
+    if out.dtype != dtype or out.numel() != n or not out.is_contiguous() or out.device != device:
+        raise ValueError(f"out must be a contiguous {dtype} tensor of {n} elements on {device}")
+    return out
+
+
+def mk_ii(shape: torch.Tensor, n: int, out_dtype=torch.int64, ws_tag: str = "shape_tools",
+          out: Optional[torch.Tensor] = None) -> torch.Tensor:
     """mkII: the row number of every element of rows of the given sizes."""
     _check_dev(shape)
     shape = shape.contiguous()
     m = shape.numel()
-    out = torch.empty(n, dtype=out_dtype, device=shape.device)
+    out = _tool_out(out, n, out_dtype, shape.device)
     ws = workspace(L.lib().ixp_mk_ii_workspace(n, m), shape.device, ws_tag)
     rc = L.lib().ixp_mk_ii(_ptr(shape), m, n, _ptr(out), _IDX_T[out_dtype], _ptr(ws), ws.numel(),
                            _stream_ptr(shape.device))
@@ -266,13 +275,14 @@ def mk_ii(shape: torch.Tensor, n: int, out_dtype=torch.int64, ws_tag: str = "sha
     return out
 
 
-def mk_sgm_descr(shape: torch.Tensor, xs: torch.Tensor, n: int, ws_tag: str = "shape_tools") -> torch.Tensor:
+def mk_sgm_descr(shape: torch.Tensor, xs: torch.Tensor, n: int, ws_tag: str = "shape_tools",
+                 out: Optional[torch.Tensor] = None) -> torch.Tensor:
     """mkSgmDescr: xs[k] at the first position of every non-empty row k, 0 elsewhere."""
     _check_dev(shape, xs)
     shape = shape.contiguous()
     xs = xs.contiguous().to(torch.int64)
     m = shape.numel()
-    out = torch.empty(n, dtype=torch.int64, device=shape.device)
+    out = _tool_out(out, n, torch.int64, shape.device)
     ws = workspace(L.lib().ixp_mk_ii_workspace(n, m), shape.device, ws_tag)
     rc = L.lib().ixp_mk_sgm_descr(_ptr(shape), m, n, _ptr(xs), _ptr(out), _ptr(ws), ws.numel(),
                                   _stream_ptr(shape.device))

@@ -39,6 +39,26 @@ def test_random_shapes(seed):
         _both(W.segment_sizes(m, 300 + seed, median_log2=med, sigma_log2=sig, empty_frac=empty))
 
 
+@pytest.mark.parametrize("offset", [0, 1, 2, 3])
+def test_outputs_not_16_byte_aligned(offset):
+    """Outputs starting 1..3 elements past a 16-byte boundary take the
+    element-wise stores; the aligned case takes 16-byte groups."""
+    shape = W.segment_sizes(700, 77, median_log2=8, sigma_log2=2.0, empty_frac=0.2)
+    n = int(shape.sum())
+    st = torch.from_numpy(shape).to(DEV)
+    xs = np.arange(len(shape), dtype=np.int64) * 5 + 1
+    print(f"[shape-tools] offset={offset} n={n}", flush=True)
+    for dt in (torch.int32, torch.int64):
+        buf = torch.full((n + 8,), -9, dtype=dt, device=DEV)
+        ii = P.mk_ii(st, n, dt, out=buf[offset:offset + n])
+        assert np.array_equal(ii.cpu().numpy().astype(np.int64), O.mk_ii(shape))
+        assert (buf[:offset] == -9).all() and (buf[offset + n:] == -9).all()
+    buf = torch.full((n + 8,), -9, dtype=torch.int64, device=DEV)
+    d = P.mk_sgm_descr(st, torch.from_numpy(xs).to(DEV), n, out=buf[offset:offset + n])
+    assert np.array_equal(d.cpu().numpy(), O.mk_sgm_descr(shape, xs))
+    assert (buf[:offset] == -9).all() and (buf[offset + n:] == -9).all()
+
+
 def test_degenerate_and_bad_shapes():
     _both([])
     _both([0, 0])
