@@ -67,17 +67,28 @@ __device__ __forceinline__ int64_t block_sum_1024(int64_t x, int64_t *lds16) {
     return r;
 }
 
+// The 8 flags of a thread's 8 consecutive elements, as one 8-byte load when
+// the flag array is 8-byte aligned and the group lies inside [0, len).
+__device__ __forceinline__ uint64_t flag_group(const uint8_t *f, int64_t p, int64_t len, bool vec) {
+    if (vec && p + 8 <= len) return *reinterpret_cast<const uint64_t *>(f + p);
+    uint64_t x = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        if (p + k < len) x |= static_cast<uint64_t>(f[p + k]) << (8 * k);
+    return x;
+}
+
 __global__ __launch_bounds__(kSgThreads) void sg_reduce_kernel(SgArgs a) {
     __shared__ int64_t lds[16];
     const int64_t c = blockIdx.x;
     const int64_t lo = c * a.chunk;
     const int64_t hi = lo + a.chunk < a.n ? lo + a.chunk : a.n;
-    // last flagged position of the chunk (lo - 1 if none), from 4 flag bytes per thread and step
+    // last flagged position of the chunk (lo - 1 if none), from 8 flag bytes per thread and step
     int64_t last = lo - 1;
-    for (int64_t p = lo + static_cast<int64_t>(threadIdx.x) * 4; p < hi; p += kSgThreads * 4) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-            if (p + q < hi && a.flags[p + q] != 0) last = p + q;
+    const bool fvec = (reinterpret_cast<uintptr_t>(a.flags) & 7) == 0;
+    for (int64_t p = static_cast<int64_t>(threadIdx.x) * 8; lo + p < hi; p += kSgThreads * 8) {
+        const uint64_t fg = flag_group(a.flags + lo, p, hi - lo, fvec);
+        if (fg) last = lo + p + (63 - __builtin_clzll(fg)) / 8;
     }
     last = block_max_1024(last, lds);
     // a flagged element restarts the sum with its own value
@@ -133,8 +144,8 @@ __global__ __launch_bounds__(1024) void sg_chunk_scan_kernel(SgArgs a) {
 }
 
 __global__ __launch_bounds__(kSgThreads) void sg_rescan_kernel(SgArgs a) {
+    static_assert(kSgPer == 8, "one 8-byte flag group per thread");
     __shared__ int64_t sv[kSgTile];
-    __shared__ uint8_t sf[kSgTile];
     __shared__ int64_t wv[kSgThreads / kWave];
     __shared__ int32_t wf[kSgThreads / kWave];
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = wave_id();
@@ -142,13 +153,14 @@ __global__ __launch_bounds__(kSgThreads) void sg_rescan_kernel(SgArgs a) {
     const int64_t lo_c = c * a.chunk;
     const int64_t hi_c = lo_c + a.chunk < a.n ? lo_c + a.chunk : a.n;
     int64_t carry = a.agg_v[c];   // value before the chunk (a flag inside the chunk resets it)
+    const bool fvec = (reinterpret_cast<uintptr_t>(a.flags) & 7) == 0;
     for (int64_t lo = lo_c; lo < hi_c; lo += kSgTile) {
         const int64_t len = hi_c - lo < kSgTile ? hi_c - lo : kSgTile;
+        const uint64_t fg = flag_group(a.flags + lo, static_cast<int64_t>(tid) * kSgPer, len, fvec);
 #pragma unroll
         for (int k = 0; k < kSgPer; ++k) {
             const int l = k * kSgThreads + tid;
             sv[l] = l < len ? __builtin_nontemporal_load(a.xs + lo + l) : 0;
-            sf[l] = l < len ? a.flags[lo + l] : 0;
         }
         __syncthreads();
         Pair run{false, 0};
@@ -156,7 +168,7 @@ __global__ __launch_bounds__(kSgThreads) void sg_rescan_kernel(SgArgs a) {
 #pragma unroll
         for (int k = 0; k < kSgPer; ++k) {
             const int l = tid * kSgPer + k;
-            run = combine(run, Pair{sf[l] != 0, sv[l]});
+            run = combine(run, Pair{((fg >> (8 * k)) & 0xFFu) != 0, sv[l]});
             el[k] = run;
         }
         Pair inc = run;

@@ -79,6 +79,23 @@ def test_sgm_sum_matches_oracle(n, density):
     assert np.array_equal(got.cpu().numpy(), O.sgm_sum(flags, xs))
 
 
+@pytest.mark.parametrize("offset", [0, 1, 3, 7])
+def test_sgm_sum_flags_not_8_byte_aligned(offset):
+    """Flag arrays starting 1..7 bytes past an 8-byte boundary are read byte
+    by byte, aligned ones 8 bytes per thread; both over several chunks and a
+    ragged last tile."""
+    n = 3 * 8192 * 5 + 1234
+    g = np.random.default_rng(900 + offset)
+    flags = (g.random(n) < 3e-4).astype(np.uint8)
+    flags[8191] = 1   # last element of a tile
+    xs = g.integers(-2**40, 2**40, n)
+    print(f"[sgm_sum] offset={offset} n={n}", flush=True)
+    buf = torch.zeros(n + 16, dtype=torch.uint8, device=DEV)
+    buf[offset:offset + n] = torch.from_numpy(flags).to(DEV)
+    got = P.sgm_sum(buf[offset:offset + n], torch.from_numpy(xs).to(DEV))
+    assert np.array_equal(got.cpu().numpy(), O.sgm_sum(flags, xs))
+
+
 def test_sgm_sum_builds_mk_ii():
     """mkII as the paper builds it: sgmSum over the segment descriptor of the
     row numbers (row k at o_k, 0 elsewhere; flags where it is nonzero)."""
