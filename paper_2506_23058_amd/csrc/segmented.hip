@@ -24,7 +24,9 @@
 //                dense array of item counts;
 //   seg_scan_items / seg_item_bases -- one scan of all item counts, then per
 //                item its output bases and T_k of its row;
-//   seg_main  -- persistent workgroups take items round-robin; each
+//   seg_main  -- workgroups take items round-robin (the default grid of 64
+//                workgroups per CU oversubscribes the chip, so the hardware
+//                starts the items in order as slots free); each
 //                loads its item, ranks the trues by ballot/mbcnt, writes the
 //                indices and descriptor bytes in input order and the keys,
 //                staged in LDS, as two contiguous runs.  A row that fits one
@@ -419,9 +421,9 @@ __device__ __forceinline__ void row_counts(const SegArgs &a, const Pred &pred, i
     }
 }
 
-// Persistent workgroups take items round-robin (item = blockIdx.x + k *
-// gridDim.x: no shared queue counter, whose serialised atomics would cost
-// ~10 ns per item).  Wave 0 prefetches the next item's 48-byte descriptor,
+// Workgroups take items round-robin (item = blockIdx.x + k * gridDim.x: no
+// shared queue counter, whose serialised atomics would cost ~10 ns per
+// item); a grid smaller than the item count makes them persistent.  Wave 0 prefetches the next item's 48-byte descriptor,
 // one 8-byte word per lane, while the workgroup processes the current one.
 template <int BLOCK, int ROWS, class Pred, int MODE, class Idx>
 __global__ __launch_bounds__(BLOCK) void seg_main_kernel(SegArgs a, Pred pred) {
