@@ -137,6 +137,31 @@ extern "C" const char *ixp_status_str(int status) {
     }
 }
 
+namespace ixp {
+size_t lds_for_wgs_per_cu(int wgs, size_t static_lds) {
+    static std::mutex mu;
+    static int cached[64] = {0};
+    int dev = 0;
+    if (wgs < 1 || hipGetDevice(&dev) != hipSuccess || dev < 0) return 0;
+    int lds = 0;
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        if (dev < 64) lds = cached[dev];
+    }
+    if (lds <= 0) {
+        if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess ||
+            lds <= 0)
+            return 0;
+        std::lock_guard<std::mutex> lock(mu);
+        if (dev < 64) cached[dev] = lds;
+    }
+    // per-workgroup total in (lds / (wgs + 1), lds / wgs], on a 2 KiB boundary
+    const size_t per_wg = (static_cast<size_t>(lds) / static_cast<size_t>(wgs)) & ~static_cast<size_t>(2047);
+    if (per_wg * static_cast<size_t>(wgs + 1) <= static_cast<size_t>(lds) || per_wg <= static_lds) return 0;
+    return per_wg - static_lds;
+}
+}  // namespace ixp
+
 extern "C" int ixp_device_cus(void) { return ixp::device_cus(); }
 
 // Every workspace starts with the same 256-byte header: a u32 ticket at

@@ -89,6 +89,12 @@ struct FlatArgs {
 // depend on the device).
 constexpr int64_t kCountWaves = 8192;
 
+// Resident partition-scatter workgroups per CU.  Fewer tiles in flight means
+// fewer interleaved output streams (an index run and two key runs per tile):
+// measured on 2^28 f32, 3 per CU takes 548 us where the 7 that registers and
+// LDS allow take 584 us (2 per CU: 565 us, 4: 581 us).
+constexpr int kScatterWgsPerCu = 3;
+
 __global__ void flat_init_kernel(uint32_t *ticket, int32_t *err, uint64_t *desc, int64_t num_desc) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i == 0) {
@@ -301,12 +307,14 @@ int launch_flat(FlatArgs a, const Pred &pred, int mode, int idx_t, hipStream_t s
         IXP_LAUNCH("flat_tile_scan", flat_tile_scan_kernel, dim3(1), dim3(1024), 0, st, a.wsum, nw,
                    a.split, a.err);
         if (nt == 0) return launch_status();
+        // at most kScatterWgsPerCu scatter workgroups per CU (LDS reserved at launch)
+        const size_t cap = VEC == 4 ? lds_for_wgs_per_cu(kScatterWgsPerCu, Cfg::kTile * 4 + 256) : 0;
         if (idx_t == IXP_I32)
             IXP_LAUNCH("flat_scatter_partition", (flat_scan_kernel<VEC, Pred, IXP_MODE_PARTITION, int32_t>),
-                       dim3(static_cast<uint32_t>(nt)), dim3(Cfg::kBlock), 0, st, a, pred);
+                       dim3(static_cast<uint32_t>(nt)), dim3(Cfg::kBlock), cap, st, a, pred);
         else
             IXP_LAUNCH("flat_scatter_partition", (flat_scan_kernel<VEC, Pred, IXP_MODE_PARTITION, int64_t>),
-                       dim3(static_cast<uint32_t>(nt)), dim3(Cfg::kBlock), 0, st, a, pred);
+                       dim3(static_cast<uint32_t>(nt)), dim3(Cfg::kBlock), cap, st, a, pred);
     } else {
         using Cfg = FlatCfg<IXP_MODE_FILTER, VEC>;
         a.num_tiles = ceil_div(n, Cfg::kTile);

@@ -71,6 +71,11 @@ inline bool is_row_pred(int kind) { return kind == IXP_PRED_LT_ROW || kind == IX
 // Number of compute units of the current device, cached per device.
 int device_cus();
 
+// Dynamic LDS bytes to request at launch so that at most `wgs` workgroups of a
+// kernel with `static_lds` bytes of static LDS fit on one CU (an occupancy
+// cap), from the current device's LDS per CU; 0 when it cannot be applied.
+size_t lds_for_wgs_per_cu(int wgs, size_t static_lds);
+
 // Kernel timing: while profiling is enabled, a ProfScope records a HIP event
 // on `st` at construction and another at destruction, around one launch.
 bool profiling();
