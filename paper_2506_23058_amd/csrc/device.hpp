@@ -63,6 +63,18 @@ __device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int lane) {
     return (static_cast<uint64_t>(hi) << 32) | lo;
 }
 
+// Tile of workgroup b among nt tiles in an XCD-aware order.  The hardware
+// deals workgroups round-robin to the 8 XCDs; this gives each XCD one
+// contiguous range of tiles (the first nt - 8 (per - 1) XCDs take `per`
+// tiles, the others per - 1), so neighbouring tiles' output runs and the
+// partial cache lines between them meet in one L2.  A bijection of [0, nt).
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nt) {
+    const int64_t per = (nt + 7) / 8;
+    const int64_t x = b % 8, k = b / 8;
+    const int64_t full = nt - (per - 1) * 8;   // XCDs that take `per` tiles
+    return x < full ? x * per + k : full * per + (x - full) * (per - 1) + k;
+}
+
 // ---------------------------------------------------------------- predicates --
 // Keys travel as raw 32-bit words; each predicate interprets them.
 

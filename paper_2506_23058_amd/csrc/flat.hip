@@ -201,14 +201,7 @@ __global__ __launch_bounds__((FlatCfg<MODE, VEC>::kBlock)) void flat_scan_kernel
     int64_t t;
     if (MODE == IXP_MODE_PARTITION) {
 #if IXP_XCD_MAP
-        // workgroups are dealt round-robin to the 8 XCDs; give each XCD a
-        // contiguous range of tiles, so neighbouring output runs (and the
-        // partial lines between them) meet in one L2
-        const int64_t nt = a.num_tiles;
-        const int64_t per = (nt + 7) / 8;
-        const int64_t x = blockIdx.x % 8, k = blockIdx.x / 8;
-        const int64_t full = nt - (per - 1) * 8;   // XCDs that get `per` tiles (the rest get per - 1)
-        t = x < full ? x * per + k : full * per + (x - full) * (per - 1) + k;
+        t = xcd_tile(blockIdx.x, a.num_tiles);
 #else
         t = blockIdx.x;
 #endif
