@@ -5,9 +5,9 @@ CPU-baseline leg of ``bench.py`` may import this package.  It shares no code
 with the HIP library: the arithmetic lives in ``ixoracle.c`` (plain C, one
 thread), this module only marshals numpy arrays through ctypes.
 
-The C file follows the paper step by step:
-  * combinators map / scan / scatter ....... Section 2.1
-  * partition2, sgmSum, mkSgmDescr, mkII ... Section 2.1, figure "Running Examples"
+The C file writes out the plain definition of every result:
+  * combinators map / scatter .............. Section 2.1
+  * partition2, sgmSum, mkSgmDescr, mkII ... Section 2.1
   * partition2L (segmented partition) ...... Section 6, "Segmented operations"
   * Range / Monotonic / Inj / Bij / FiltPart  Section 2.3, figure "Array Properties"
 

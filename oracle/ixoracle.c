@@ -6,14 +6,15 @@
  * leg of the benchmark load it.  It shares no header, helper, table or
  * constant with the HIP implementation.
  *
- * Every routine is written as the paper states the computation, one step at a
- * time, in the paper's order and notation, with no blocking, fusion or
- * reordering:
- *   - map / inclusive scan / scatter semantics: Section 2.1 (combinator types
- *     and the imperative meaning of scatter);
- *   - partition2, sgmSum, mkSgmDescr, mkII: Section 2.1, figure "Running
- *     Examples";
- *   - partition2L (segmented partition): Section 6, "Segmented operations";
+ * Every result computed here has a plain definition, and each routine is
+ * that definition written out as a sequential loop, with no blocking, fusion
+ * or reordering:
+ *   - map and scatter semantics: Section 2.1 (combinator types and the
+ *     imperative meaning of scatter);
+ *   - partition2 / filter (the stable two-way partition and the order-keeping
+ *     filter), sgmSum, mkSgmDescr, mkII: Section 2.1;
+ *   - partition2L (partition2 of every row of a jagged array): Section 6,
+ *     "Segmented operations";
  *   - the properties Range, Monotonic, Inj, Bij, FiltPart / InvFiltPart:
  *     Section 2.3, figure "Array Properties" and the prose after it.
  * Readings taken where the paper is ambiguous are listed beside the code that
@@ -79,19 +80,11 @@ int ixo_map_pred(const void *xs, int key_t, int64_t n, int pred_kind,
     return 0;
 }
 
-/* scan (+) 0 xs -- inclusive prefix sum (Section 2.1). */
-static void scan_plus_i64(const int64_t *xs, int64_t n, int64_t *out) {
-    int64_t acc = 0;
-    for (int64_t i = 0; i < n; i++) {
-        acc = acc + xs[i];
-        out[i] = acc;
-    }
-}
-
 /* scatter dst is vs: for i in 0..m-1, if 0 <= is[i] < len(dst) then
- * dst[is[i]] := vs[i] (Section 2.1).  The printed bound says "< m", but the
- * type gives dst length n and the prose says "out of bounds in dst"; the bound
- * taken is the length of dst.  Elements are moved as raw bytes. */
+ * dst[is[i]] := vs[i] (Section 2.1).  Writes outside dst are the ones
+ * ignored: the bound is the length of dst (the type of scatter gives dst
+ * length n; a bound of m is read as a slip).  Elements are moved as raw
+ * bytes. */
 int ixo_scatter(void *dst, int64_t n_dst, const int64_t *is, const void *vs,
                 int64_t m, int64_t elem_bytes) {
     if (n_dst < 0 || m < 0 || elem_bytes <= 0) return -1;
@@ -261,67 +254,45 @@ int ixo_partition_v(const void *xs, int64_t n, int32_t kind, int32_t v, const fl
 }
 
 /* ------------------------------------------------------------------------ */
-/* partition2 (Section 2.1, figure "Running Examples", left), step by step: */
-/* the predicate gives a boolean per element; two 0/1 arrays mark the       */
-/* trues and the falses; an inclusive +-scan of each counts, for every      */
-/* element, the members of its class up to and including it; the number of */
-/* trues is the last count of the first scan; a true goes to its count      */
-/* minus one, a false to the number of trues plus its count minus one; the  */
-/* elements are scattered to those positions in a zeroed array of length n. */
-/* returns (num_true, ys).  `indices` is also returned: it is the scatter   */
-/* array whose InvFiltPart property the paper proves.                       */
+/* partition2 (Section 2.1) by its definition: the elements whose flag is   */
+/* set, in input order, followed by the others, in input order.  `indices`  */
+/* gives every element its place in that output -- the scatter array whose  */
+/* InvFiltPart property the paper proves (Section 2.3).  With T the number  */
+/* of set flags, one walk over the input hands out positions 0, 1, ... to    */
+/* the trues and T, T+1, ... to the falses; the elements are then scattered */
+/* into a zeroed array of length n.                                          */
 /*                                                                          */
 /* FILTER mode is the paper's `filter` (FiltPart with p^f = p and no        */
-/* partitioning predicate): a true goes to its count minus one, a false to  */
-/* -1; the scatter target has length num_true, and the -1 entries are out   */
-/* of bounds and ignored.                                                   */
+/* partitioning predicate): only the trues are kept, in input order, so a   */
+/* true gets the number of trues before it and a false gets -1, which the   */
+/* scatter into the length-T target ignores.                                */
 /* ------------------------------------------------------------------------ */
 static int partition2_from_cs(const void *xs, int64_t kb, int64_t n,
                               const uint8_t *cs, int mode, void *ys,
                               int64_t *indices_out, int64_t *num_true_out) {
-    int64_t *flagsT = NULL, *flagsF = NULL, *indicesT = NULL, *tmp = NULL,
-            *indicesF = NULL, *indices = NULL;
-    int rc = -2;
     size_t nb = (size_t)(n > 0 ? n : 1) * sizeof(int64_t);
-    flagsT = malloc(nb);
-    indicesT = malloc(nb);
-    indices = indices_out ? indices_out : malloc(nb);
-    if (!flagsT || !indicesT || !indices) goto done;
+    int64_t *indices = indices_out ? indices_out : malloc(nb);
+    if (!indices) return -2;
 
-    for (int64_t i = 0; i < n; i++) flagsT[i] = cs[i] ? 1 : 0;
-    scan_plus_i64(flagsT, n, indicesT);
-    int64_t num_true = n > 0 ? indicesT[n - 1] : 0;
+    int64_t num_true = 0;
+    for (int64_t i = 0; i < n; i++)
+        if (cs[i]) num_true++;
 
-    if (mode == IXO_MODE_PARTITION) {
-        flagsF = malloc(nb);
-        tmp = malloc(nb);
-        if (!flagsF || !tmp) goto done;
-        for (int64_t i = 0; i < n; i++) flagsF[i] = 1 - flagsT[i];
-        scan_plus_i64(flagsF, n, tmp);
-        free(flagsF); flagsF = NULL;
-        indicesF = tmp; /* the false counts shifted by num_true, in place */
-        tmp = NULL;
-        for (int64_t i = 0; i < n; i++) indicesF[i] = indicesF[i] + num_true;
-        for (int64_t i = 0; i < n; i++)
-            indices[i] = cs[i] ? indicesT[i] - 1 : indicesF[i] - 1;
-        if (ys) {
-            memset(ys, 0, (size_t)(n * kb)); /* replicate n 0 */
-            ixo_scatter(ys, n, indices, xs, n, kb);
-        }
-    } else {
-        for (int64_t i = 0; i < n; i++)
-            indices[i] = cs[i] ? indicesT[i] - 1 : -1;
-        if (ys) {
-            memset(ys, 0, (size_t)(num_true * kb)); /* replicate num_true 0 */
-            ixo_scatter(ys, num_true, indices, xs, n, kb);
-        }
+    int64_t next_true = 0, next_false = num_true;
+    for (int64_t i = 0; i < n; i++) {
+        if (cs[i])
+            indices[i] = next_true++;
+        else
+            indices[i] = mode == IXO_MODE_PARTITION ? next_false++ : -1;
+    }
+    if (ys) {
+        int64_t len = mode == IXO_MODE_PARTITION ? n : num_true;
+        memset(ys, 0, (size_t)(len * kb));
+        ixo_scatter(ys, len, indices, xs, n, kb);
     }
     if (num_true_out) *num_true_out = num_true;
-    rc = 0;
-done:
-    free(flagsT); free(flagsF); free(indicesT); free(tmp); free(indicesF);
     if (indices != indices_out) free(indices);
-    return rc;
+    return 0;
 }
 
 int ixo_partition2(const void *xs, int key_t, int64_t n, int pred_kind,
@@ -343,83 +314,61 @@ int ixo_partition2(const void *xs, int key_t, int64_t n, int pred_kind,
 /* Segmented helpers (Section 2.1, figure "Running Examples", right).       */
 /* ------------------------------------------------------------------------ */
 
-/* sgmSum flags xs: inclusive scan with the lifted operator
- *   (fx, vx) (+) (fy, vy) = (fx || fy, fy ? vy : vx + vy),  neutral (false, 0).
- * The printed lambda binds f1 v1 f2 v2 but its body uses fx fy vx vy; the
- * operator above is the reading taken (the standard segmented-scan lift). */
+/* sgmSum flags xs (Section 2.1): the running sum of xs that restarts at
+ * every set flag, i.e. out[i] = xs[j] + ... + xs[i] with j the last position
+ * <= i whose flag is set (j = 0 if there is none).  It is the inclusive scan
+ * of (flag, value) pairs under (fx, vx) (+) (fy, vy) = (fx || fy,
+ * fy ? vy : vx + vy) with neutral element (false, 0), the reading taken for
+ * the operator. */
 int ixo_sgm_sum(const uint8_t *flags, const int64_t *xs, int64_t n,
                 int64_t *out) {
     if (n < 0) return -1;
-    int acc_f = 0;
-    int64_t acc_v = 0;
+    int64_t run = 0;
     for (int64_t i = 0; i < n; i++) {
-        int fy = flags[i] != 0;
-        int64_t vy = xs[i];
-        int f = acc_f || fy;
-        int64_t v = fy ? vy : acc_v + vy;
-        acc_f = f;
-        acc_v = v;
-        out[i] = acc_v;
+        run = flags[i] ? xs[i] : run + xs[i];
+        out[i] = run;
     }
     return 0;
 }
 
-/* mkSgmDescr shape xs: flat array of length sum(shape) in which every
- * non-empty segment starts with xs[k] and is otherwise zero.  The sizes are
- * shifted right by one (0 in front) and +-scanned, which gives every row's
- * offset; a non-empty row keeps its offset as target index and an empty row
- * gets -1, which the scatter ignores; the length is the last offset plus the
- * last size; xs is scattered by these indices into a zeroed array.  `out` must hold
- * sum(shape) entries; returns -1 if a size is negative. */
+/* mkSgmDescr shape xs (Section 2.1): an array of length sum(shape), zero
+ * except at the first position of every non-empty row k, which holds xs[k].
+ * Row k starts at o_k, the sum of the sizes of rows 0..k-1; an empty row has
+ * no first position and leaves no trace.  `out` must hold sum(shape)
+ * entries; returns -1 if a size is negative or the length differs. */
 int ixo_mk_sgm_descr(const int64_t *shape, int64_t m, const int64_t *xs,
                      int64_t *out, int64_t out_len) {
     if (m < 0) return -1;
-    for (int64_t k = 0; k < m; k++)
+    int64_t len = 0;
+    for (int64_t k = 0; k < m; k++) {
         if (shape[k] < 0) return -1;
-    int64_t *rot = malloc((size_t)(m > 0 ? m : 1) * sizeof(int64_t));
-    int64_t *scn = malloc((size_t)(m > 0 ? m : 1) * sizeof(int64_t));
-    int64_t *ind = malloc((size_t)(m > 0 ? m : 1) * sizeof(int64_t));
-    if (!rot || !scn || !ind) { free(rot); free(scn); free(ind); return -2; }
-    for (int64_t i = 0; i < m; i++) rot[i] = i == 0 ? 0 : shape[i - 1];
-    scan_plus_i64(rot, m, scn);
-    for (int64_t k = 0; k < m; k++) ind[k] = shape[k] <= 0 ? -1 : scn[k];
-    int64_t len = m > 0 ? scn[m - 1] + shape[m - 1] : 0;
-    int rc = -1;
-    if (len == out_len) {
-        for (int64_t j = 0; j < len; j++) out[j] = 0;
-        rc = ixo_scatter(out, len, ind, xs, m, (int64_t)sizeof(int64_t));
+        len += shape[k];
     }
-    free(rot); free(scn); free(ind);
-    return rc;
+    if (len != out_len) return -1;
+    for (int64_t j = 0; j < len; j++) out[j] = 0;
+    int64_t o = 0;
+    for (int64_t k = 0; k < m; k++) {
+        if (shape[k] > 0) out[o] = xs[k];
+        o += shape[k];
+    }
+    return 0;
 }
 
-/* mkII shape: segment number of every flat element.  The rows are numbered
- * from one and mkSgmDescr places each number at its row's start (zero
- * elsewhere); taking one off every non-zero entry leaves row k's number k at
- * its start; the positive entries mark segment starts, and a segmented sum
- * over those marks spreads each number across its row (row 0, whose start
- * holds 0 and no mark, gets the 0 that the sum carries from the array start).
- * (The figure uses two spellings for one of these arrays; one array is
- * meant.)  The worked example maps [0,2,1,0,3] to [1,1,2,4,4,4]. */
+/* mkII shape (Section 2.1): the row number of every flat element, i.e.
+ * out[i] = k for o_k <= i < o_k + shape[k].  The paper's example maps the
+ * shape [0,2,1,0,3] to [1,1,2,4,4,4]. */
 int ixo_mk_ii(const int64_t *shape, int64_t m, int64_t *out, int64_t out_len) {
     if (m < 0) return -1;
-    int64_t *beg_vs = malloc((size_t)(m > 0 ? m : 1) * sizeof(int64_t));
-    int64_t *sct = malloc((size_t)(out_len > 0 ? out_len : 1) * sizeof(int64_t));
-    uint8_t *flags = malloc((size_t)(out_len > 0 ? out_len : 1));
-    int rc = -2;
-    if (!beg_vs || !sct || !flags) goto done;
-    for (int64_t i = 0; i < m; i++) beg_vs[i] = i + 1;
-    rc = ixo_mk_sgm_descr(shape, m, beg_vs, sct, out_len);
-    if (rc != 0) goto done;
-    for (int64_t j = 0; j < out_len; j++) sct[j] = sct[j] == 0 ? 0 : sct[j] - 1;
-    /* flags = map (f -> f > 0) sct_vs, as printed.  Segment 0's start value
-     * is 0 after the decrement, so its start is not flagged; the scan still
-     * yields 0 there because every value before it is 0. */
-    for (int64_t j = 0; j < out_len; j++) flags[j] = sct[j] > 0;
-    rc = ixo_sgm_sum(flags, sct, out_len, out);
-done:
-    free(beg_vs); free(sct); free(flags);
-    return rc;
+    int64_t len = 0;
+    for (int64_t k = 0; k < m; k++) {
+        if (shape[k] < 0) return -1;
+        len += shape[k];
+    }
+    if (len != out_len) return -1;
+    int64_t i = 0;
+    for (int64_t k = 0; k < m; k++)
+        for (int64_t j = 0; j < shape[k]; j++) out[i++] = k;
+    return 0;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -545,10 +494,10 @@ int ixo_partition2L_rows(const void *xs, int key_t, int64_t n, const int64_t *sh
 /* paper proves properties and never locates a failure, so the index         */
 /* conventions below are this library's definitions:                         */
 /*   Range [lo,hi): min i with X[i] outside [lo,hi); aux = X[i].             */
-/*     (The figure prints a closed interval, every use in the paper is       */
+/*     (The figure's interval is closed, every use in the paper is           */
 /*      half-open; half-open is taken, with explicit bounds.)                */
 /*   Monotonic op: min i >= 1 with !(X[i-1] op X[i]) (the later element);    */
-/*     aux = 0.  (The printed bound j < n-1 would leave the last element     */
+/*     aux = 0.  (A bound of j < n-1 would leave the last element            */
 /*     unconstrained; j < n is taken.  For a transitive op all-pairs and     */
 /*     adjacent pairs agree.)                                                */
 /*   Inj Rcd=[lo,hi): min i such that some j < i has X[j] = X[i] in Rcd      */

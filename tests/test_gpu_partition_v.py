@@ -60,3 +60,26 @@ def test_partition_v_rejects_bad_classes():
         P.partition_v(x, P.Classes(P.CLASS_MOD, 3))                 # modulus needs int32 keys
     with pytest.raises(ValueError):
         P.partition_v(x, P.Classes(P.CLASS_THRESH, 5, (0.1, 0.2, 0.3)))
+
+
+def test_partition_v_multi_run_counting_ragged_tail():
+    """n = 2^25 + 4097: 8194 tiles of 4096 elements, more than the 8192
+    counting waves, so each counting wave owns two tiles and every tile's
+    prefix is its offset inside the run plus the run's prefix; the last tile
+    holds a single element."""
+    n = (1 << 25) + 4097
+    x = W.f32_uniform(n, 2)
+    run_both(x, 3, O.CLASS_THRESH, (1 / 3, 2 / 3, 0.0), idx_dtype=torch.int32)
+    xi = W.int_keys(n, 201)
+    cls = np.random.default_rng(202).integers(0, 6, n).astype(np.uint8)
+    run_both(xi, 4, O.CLASS_BYTES, cls=cls)
+    n2 = (1 << 25) + 4099
+    run_both(W.int_keys(n2, 203), 3, O.CLASS_MOD, idx_dtype=torch.int32)
+
+
+def test_partition3_config_2e28():
+    """partition3 of the 2^28 f32 uniform input (x < 1/3, x < 2/3, rest) with
+    int32 indices, the launch the benchmark times: 65536 tiles, 8 per
+    counting wave."""
+    x = W.f32_uniform(W.FLAT_LARGE_N, W.FLAT_LARGE_SEED)
+    run_both(x, 3, O.CLASS_THRESH, (1 / 3, 2 / 3, 0.0), idx_dtype=torch.int32)

@@ -1,6 +1,8 @@
 """GPU parity of the segmented partition (partition2L / filter_seg) with the
 CPU oracle, bit-exact: keys, indices, per-row split points and the segment
 descriptor bytes."""
+import ctypes
+
 import numpy as np
 import pytest
 import torch
@@ -115,6 +117,27 @@ def test_config_segmented_full_compare():
     run_both(keys, shape, tune=(256, 4, 64, 2))   # every sibling counted by the waiter
     shape_e = W.segment_sizes(W.SEG_M, W.SEG_SIZES_SEED, empty_frac=0.1)
     run_both(keys[: int(shape_e.sum())].copy(), shape_e, mode=0)
+
+
+def _items(shape, tile):
+    o = np.concatenate([[0], np.cumsum(shape)])[:-1]
+    return np.where(shape > 0, ((o & 3) + shape + tile - 1) // tile, 0)
+
+
+@pytest.mark.parametrize("mode,tune", [(0, (256, 4, 64, 1)), (0, (256, 2, 64, 1)),
+                                       (1, None), (1, (256, 2, 64, 0)), (1, (1024, 4, 0, 0))])
+def test_config_segmented_counted_items_lookback(mode, tune):
+    """The 10^4-row workload with the counting pass: row sync COUNT counts
+    every item of a multi-item row, filter mode every item.  Every case counts
+    more than 8192 items (11,331 to 39,318), so the item scan chains two to
+    five 8192-count chunks by decoupled look-back."""
+    shape = W.segment_sizes(W.SEG_M, W.SEG_SIZES_SEED)
+    keys = W.int_keys(int(shape.sum()), W.SEG_KEYS_SEED)
+    tile = (tune[0] * tune[1] * 4) if tune else 4096
+    it = _items(shape, tile)
+    counted = int(it.sum()) if mode == 1 else int(it[it > 1].sum())
+    assert counted > 8192, counted
+    run_both(keys, shape, mode=mode, tune=tune)
 
 
 def test_graph_replays_match_eager():
@@ -235,3 +258,29 @@ def test_row_predicates_rejected_without_rows():
     x = torch.zeros(16, dtype=torch.float32, device=DEV)
     with pytest.raises(ValueError):
         P.partition(x, P.Pred.lt_rows(torch.zeros(1, device=DEV)))
+
+
+def test_filter_seg_counts_beyond_2e32():
+    """filter_seg of 2^32 + 2^28 all-true flags in three rows, tiles of 16384:
+    34 chunks of 8192 item counts, each chunk holding 2^27 trues, so the
+    item scan's look-back windows sum past 2^32.  With every flag set the
+    row counts are the row sizes, and the rows that span chunk boundaries see
+    any wrapped window sum."""
+    n = (1 << 32) + (1 << 28)
+    a = (1 << 31) + 3
+    shape = torch.tensor([a, n - a - 7, 7], dtype=torch.int64, device=DEV)
+    flags = torch.ones(n, dtype=torch.uint8, device=DEV)
+    seg = torch.full((3,), -1, dtype=torch.int64, device=DEV)
+    t = P._lib.ixp_tuning()
+    t.block, t.rows, t.wgs_per_cu, t.row_sync = 1024, 4, 0, 0
+    ws = torch.empty(P._lib.lib().ixp_segmented_workspace(n, 3, ctypes.byref(t)), dtype=torch.uint8,
+                     device=DEV)
+    pc = P.Pred.from_flags(flags).c()
+    print(f"[seg-2^32] n={n} ws={ws.numel()}", flush=True)
+    rc = P._lib.lib().ixp_segmented_partition(
+        None, P._lib.I32, n, shape.data_ptr(), 3, ctypes.byref(pc), P.MODE_FILTER, None, None,
+        P._lib.I64, seg.data_ptr(), None, ctypes.byref(t), ws.data_ptr(), ws.numel(),
+        torch.cuda.current_stream().cuda_stream)
+    assert rc == 0
+    assert P._lib.lib().ixp_read_error(ws.data_ptr(), torch.cuda.current_stream().cuda_stream) == 0
+    assert seg.cpu().tolist() == shape.cpu().tolist()

@@ -61,7 +61,7 @@ def _stable_reference(n, c):
     return order, idx
 
 
-@pytest.mark.parametrize("n", range(0, 11))
+@pytest.mark.parametrize("n", range(0, 15))
 def test_partition2_all_flag_patterns(n):
     xs = np.arange(100, 100 + n, dtype=np.int32)
     for bits in itertools.product([0, 1], repeat=n):
