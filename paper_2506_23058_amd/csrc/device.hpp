@@ -177,9 +177,11 @@ constexpr uint32_t kSpinLimit = 1u << 22;
 // with a DPP reduction when every tile up to its nearest inclusive prefix has
 // published; at an unpublished one the walk re-reads from there (with a short
 // sleep).  Aggregates are below 2^32; an inclusive prefix may be any 62-bit
-// value and is added separately.  Tiles before `first` behave as an inclusive
-// prefix of 0.
-template <int LOADS = 4>
+// value and is added separately.  With WIDE = false a window's aggregates
+// must also sum below 2^32 (64 tiles of at most 2^26 each); WIDE sums the low
+// and high 16-bit halves apart, so 64 aggregates of up to 2^32 - 1 add without
+// wrapping.  Tiles before `first` behave as an inclusive prefix of 0.
+template <int LOADS = 4, bool WIDE = false>
 __device__ __forceinline__ int64_t lookback(const uint64_t *desc, int64_t t,
                                             int64_t first, int32_t *err) {
     const int lane = lane_id();
@@ -208,7 +210,12 @@ __device__ __forceinline__ int64_t lookback(const uint64_t *desc, int64_t t,
             const int firstP = mP ? __builtin_ctzll(mP) : kWave;
             const bool in = (upto >> lane) & 1ull;
             const uint32_t small = (in && lane != firstP) ? static_cast<uint32_t>(d[u] & kValMask) : 0u;
-            excl += wave_sum_u32(small);
+            if constexpr (WIDE) {
+                excl += static_cast<int64_t>(wave_sum_u32(small & 0xFFFFu)) +
+                        (static_cast<int64_t>(wave_sum_u32(small >> 16)) << 16);
+            } else {
+                excl += wave_sum_u32(small);
+            }
             if (mP) {
                 excl += static_cast<int64_t>(readlane_u64(d[u] & kValMask, firstP));
                 done = true;

@@ -308,10 +308,11 @@ __global__ __launch_bounds__(1024) void seg_scan_items_kernel(SegArgs a) {
     int64_t tot;
     const int64_t in_chunk = block_exclusive_scan_1024(sum, lds, &tot);
     if (wave == 0) {
-        // a chunk holds at most 8192 * 16384 trues: below 2^32, as the
-        // look-back's aggregates must be
+        // a chunk holds at most 8192 * 16384 = 2^27 trues: below 2^32, as the
+        // look-back's aggregates must be; 64 of them may pass 2^32, so the
+        // window sums are taken wide
         if (lane == 0 && c > 0) desc_store(a.scan_desc + c, kStA | static_cast<uint64_t>(tot));
-        const int64_t e = c == 0 ? 0 : lookback<4>(a.scan_desc, c, 0, a.err);
+        const int64_t e = c == 0 ? 0 : lookback<4, true>(a.scan_desc, c, 0, a.err);
         if (lane == 0) {
             desc_store(a.scan_desc + c, kStP | static_cast<uint64_t>(e + tot));
             sh[1] = e;
