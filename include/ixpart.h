@@ -57,7 +57,8 @@ enum {
     IXP_EHIP = -3,          /* a HIP runtime call or kernel launch failed     */
     IXP_EUNSUPPORTED = -4,  /* valid request this build does not implement    */
     IXP_EWORKSPACE = -5,    /* workspace missing or smaller than required     */
-    IXP_EDEVICE = -6        /* a kernel reported an error in the workspace    */
+    IXP_EDEVICE = -6,       /* a kernel reported an error in the workspace    */
+    IXP_ETOOLARGE = -7      /* n exceeds a fixed capacity (static scratch)    */
 };
 const char *ixp_status_str(int status);
 
@@ -118,6 +119,30 @@ int ixp_partition(const void *keys, int32_t key_t, int64_t n,
                   const ixp_pred *pred, int32_t mode, void *out_keys,
                   void *out_idx, int32_t idx_t, int64_t *d_split, void *ws,
                   size_t ws_bytes, void *stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * operation, arguments and results as ixp_partition, with the workspace
+ * replaced by a scratch array of IXP_NOALLOC_SCRATCH_BYTES bytes that the
+ * library holds in device memory on every GPU it runs on (from the loading of
+ * its code object until the process ends).  It calls no hipMalloc, hipFree or
+ * other allocating routine; the first call on a device looks up that device's
+ * copy of the array once.
+ *   n above IXP_NOALLOC_MAX_N (2,180,907,008 elements: 532,448 descriptors of
+ *   4096-element tiles) returns IXP_ETOOLARGE and enqueues nothing; every
+ *   other argument error is reported as by ixp_partition.
+ * All calls on one GPU share that GPU's scratch: calls that may overlap in
+ * time on one GPU (different streams, or host threads without ordering) race
+ * and give undefined results; calls ordered on one stream are safe.  The
+ * scratch keeps the last call's contents, and each call's kernels clear what
+ * they read before use.  A look-back that gave up (filter mode) is recorded
+ * in the scratch, where ixp_read_error cannot reach it. */
+#define IXP_NOALLOC_SCRATCH_BYTES ((size_t)4325376)
+#define IXP_NOALLOC_MAX_N ((int64_t)2180907008)
+int ixp_partition_noalloc(const void *keys, int32_t key_t, int64_t n,
+                          const ixp_pred *pred, int32_t mode, void *out_keys,
+                          void *out_idx, int32_t idx_t, int64_t *d_split,
+                          void *stream);
 
 /* ---- v-way partition (partition3) ----------------------------------------- */
 

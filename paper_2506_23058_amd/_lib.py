@@ -14,6 +14,9 @@ LIB_PATH = os.environ.get("IXP_LIB", os.path.join(_HERE, "libixpart.so"))
 
 IXP_OK, IXP_EINVAL, IXP_ENOMEM, IXP_EHIP, IXP_EUNSUPPORTED, IXP_EWORKSPACE, IXP_EDEVICE = \
     0, -1, -2, -3, -4, -5, -6
+IXP_ETOOLARGE = -7
+NOALLOC_SCRATCH_BYTES = 4325376
+NOALLOC_MAX_N = 2180907008
 I32, I64, F32, U8 = 0, 1, 2, 3
 PRED_MOD_EQ, PRED_LT, PRED_FLAGS, PRED_LT_ROW, PRED_MOD_ROW = 0, 1, 2, 3, 4
 MODE_PARTITION, MODE_FILTER = 0, 1
@@ -71,6 +74,7 @@ SIGNATURES = {
     "ixp_read_error": (ctypes.c_int, [_P, _P]),
     "ixp_partition_workspace": (_SZ, [_I64]),
     "ixp_partition": (ctypes.c_int, [_P, _I32, _I64, _PP, _I32, _P, _P, _I32, _P, _P, _SZ, _P]),
+    "ixp_partition_noalloc": (ctypes.c_int, [_P, _I32, _I64, _PP, _I32, _P, _P, _I32, _P, _P]),
     "ixp_partition_v_workspace": (_SZ, [_I64]),
     "ixp_mk_ii_workspace": (_SZ, [_I64, _I64]),
     "ixp_sgm_sum_workspace": (_SZ, [_I64]),

@@ -133,6 +133,7 @@ extern "C" const char *ixp_status_str(int status) {
     case IXP_EUNSUPPORTED: return "unsupported";
     case IXP_EWORKSPACE: return "workspace missing or too small";
     case IXP_EDEVICE: return "device-side error";
+    case IXP_ETOOLARGE: return "size exceeds the fixed capacity of the static scratch";
     default: return "unknown status";
     }
 }

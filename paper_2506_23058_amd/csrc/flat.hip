@@ -27,6 +27,8 @@
 //                its prefix by decoupled look-back over the descriptors,
 //                publishes its inclusive prefix, then writes as above.  The
 //                last tile writes T.
+#include <mutex>
+
 #include "device.hpp"
 #include "host.hpp"
 
@@ -363,9 +365,13 @@ extern "C" size_t ixp_partition_workspace(int64_t n) {
            round_up(static_cast<size_t>(nt) * sizeof(uint64_t), 256);
 }
 
-extern "C" int ixp_partition(const void *keys, int32_t key_t, int64_t n, const ixp_pred *pred,
-                             int32_t mode, void *out_keys, void *out_idx, int32_t idx_t,
-                             int64_t *d_split, void *ws, size_t ws_bytes, void *stream) {
+namespace {
+
+// The body of ixp_partition over a workspace `ws` of `ws_bytes` bytes (the
+// caller's, or the static scratch of ixp_partition_noalloc).
+int partition_impl(const void *keys, int32_t key_t, int64_t n, const ixp_pred *pred,
+                   int32_t mode, void *out_keys, void *out_idx, int32_t idx_t,
+                   int64_t *d_split, void *ws, size_t ws_bytes, void *stream) {
     if (n < 0 || !d_split) return IXP_EINVAL;
     if (mode != IXP_MODE_PARTITION && mode != IXP_MODE_FILTER) return IXP_EINVAL;
     if (idx_t != IXP_I32 && idx_t != IXP_I64) return IXP_EINVAL;
@@ -402,4 +408,53 @@ extern "C" int ixp_partition(const void *keys, int32_t key_t, int64_t n, const i
     const bool vec4 = aligned(keys, 16) && aligned(out_idx, 16) &&
                       (hp.kind != IXP_PRED_FLAGS || aligned(hp.flags, 4));
     return vec4 ? dispatch_pred<4>(a, hp, mode, idx_t, st) : dispatch_pred<1>(a, hp, mode, idx_t, st);
+}
+
+// Static scratch of ixp_partition_noalloc: one copy per device, allocated when
+// the code object is loaded and kept until the process ends.  Host code never
+// passes `scratch` itself to a kernel (on the host it only names the symbol);
+// it passes the device address hipGetSymbolAddress returns for the current
+// device.  Every kernel of the flat path clears, before use, the header words
+// and descriptors it reads, so nothing left by an earlier call is consumed.
+static __device__ __align__(256) unsigned char scratch[IXP_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per device.
+int scratch_for_current_device(void **out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return IXP_EHIP;
+    if (dev < 0 || dev >= kMaxDevices) return IXP_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return IXP_EHIP;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return IXP_OK;
+}
+
+}  // namespace
+
+extern "C" int ixp_partition(const void *keys, int32_t key_t, int64_t n, const ixp_pred *pred,
+                             int32_t mode, void *out_keys, void *out_idx, int32_t idx_t,
+                             int64_t *d_split, void *ws, size_t ws_bytes, void *stream) {
+    return partition_impl(keys, key_t, n, pred, mode, out_keys, out_idx, idx_t, d_split, ws,
+                          ws_bytes, stream);
+}
+
+extern "C" int ixp_partition_noalloc(const void *keys, int32_t key_t, int64_t n,
+                                     const ixp_pred *pred, int32_t mode, void *out_keys,
+                                     void *out_idx, int32_t idx_t, int64_t *d_split,
+                                     void *stream) {
+    if (n < 0) return IXP_EINVAL;
+    if (ixp_partition_workspace(n) > IXP_NOALLOC_SCRATCH_BYTES) return IXP_ETOOLARGE;
+    void *ws = nullptr;
+    const int rc = scratch_for_current_device(&ws);
+    if (rc != IXP_OK) return rc;
+    return partition_impl(keys, key_t, n, pred, mode, out_keys, out_idx, idx_t, d_split, ws,
+                          IXP_NOALLOC_SCRATCH_BYTES, stream);
 }

@@ -65,6 +65,14 @@ def test_host_side_validation_without_gpu():
     a = L.ixp_prop_args()
     a.lo, a.hi = 0, 1 << 28
     assert lib.ixp_check_props_workspace(1 << 28, 4, ctypes.byref(a)) >= (1 << 28) // 8
+    # the allocation-free partition: its capacity, checked before anything else
+    assert lib.ixp_partition_workspace(L.NOALLOC_MAX_N) <= L.NOALLOC_SCRATCH_BYTES
+    assert lib.ixp_partition_workspace(L.NOALLOC_MAX_N + 1) > L.NOALLOC_SCRATCH_BYTES
+    rc = lib.ixp_partition_noalloc(None, L.F32, L.NOALLOC_MAX_N + 1, ctypes.byref(p), 0, None,
+                                   None, L.I64, ctypes.addressof(split), None)
+    assert rc == L.IXP_ETOOLARGE
+    assert lib.ixp_partition_noalloc(None, L.F32, -1, ctypes.byref(p), 0, None, None, L.I64,
+                                     ctypes.addressof(split), None) == L.IXP_EINVAL
     assert lib.ixp_scatter_inj(None, 10, None, L.I64, None, 5, 6, None) == L.IXP_EINVAL
     assert lib.ixp_gather(None, None, 10, None, L.I32, 5, 16, None, None) == L.IXP_EINVAL
 
