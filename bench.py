@@ -31,34 +31,67 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBPS = 8000.0
 
 
-# Sources the flat partition kernels are compiled from: counter readings in
-# profiles/counters.json stay valid while these are unchanged.
-FLAT_SOURCES = ("flat.hip", "device.hpp", "host.hpp")
+# Sources each profiled kernel is compiled from: a counter reading in
+# profiles/counters.json stays valid while the hash of these is unchanged.
+KERNEL_SOURCES = {
+    "flat_count": ("flat.hip", "device.hpp", "host.hpp"),
+    "flat_scatter_partition": ("flat.hip", "device.hpp", "host.hpp"),
+    "flat_scan_filter": ("flat.hip", "device.hpp", "host.hpp"),
+    "seg_main_partition": ("segmented.hip", "device.hpp", "host.hpp"),
+    "scatter_rows": ("rows.hip", "device.hpp", "host.hpp"),
+    "gather_rows": ("rows.hip", "device.hpp", "host.hpp"),
+    "props_scan": ("props.hip", "device.hpp", "host.hpp"),
+    "props_check": ("props.hip", "device.hpp", "host.hpp"),
+}
+
+DIGESTS = os.path.join(ROOT, "tests", "golden", "bench_digests.json")
 
 
-def _csrc_hash():
+def sources_hash(files):
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2506_23058_amd", "csrc")
-    for f in FLAT_SOURCES:
+    for f in files:
         with open(os.path.join(d, f), "rb") as fh:
             h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
 
 
-def _traffic(kernel: str, launches_elems: int):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary, or None when it is absent or the kernels changed since."""
+def _traffic(kernel: str, elements: int):
+    """HBM bytes per launch of `kernel` (FETCH_SIZE + WRITE_SIZE, calibrated
+    against a plain copy) from the committed rocprofv3 counter summary, or
+    None when it is absent, taken on another workload, or the kernel's
+    sources changed since."""
     path = os.path.join(ROOT, "profiles", "counters.json")
-    if not os.path.exists(path):
+    if not os.path.exists(path) or kernel not in KERNEL_SOURCES:
         return None
     with open(path) as f:
         c = json.load(f)
-    if c.get("csrc_hash") != _csrc_hash():
-        return None
     k = c.get("kernels", {}).get(kernel)
-    if not k or k.get("elements") != launches_elems:
+    if not k or k.get("elements") != elements:
+        return None
+    if k.get("sources_hash") != sources_hash(KERNEL_SOURCES[kernel]):
         return None
     return k.get("hbm_bytes_per_launch")
+
+
+def _golden():
+    with open(DIGESTS) as f:
+        return json.load(f)
+
+
+def _sha(t) -> str:
+    """SHA-256 of a tensor's bytes (copied to the host)."""
+    import numpy as np
+    a = t.detach().contiguous().cpu().numpy()
+    return hashlib.sha256(np.ascontiguousarray(a).reshape(-1).view(np.uint8)).hexdigest()
+
+
+def _verify(what: str, got: dict, want: dict):
+    """Every field of `got` must equal the oracle's stored value."""
+    bad = {k: (v, want.get(k)) for k, v in got.items() if want.get(k) != v}
+    if bad:
+        raise AssertionError(f"{what}: device outputs differ from the oracle's: {sorted(bad)}")
+    return True
 
 
 def timed(fn, steps, warmup, torch):
@@ -143,6 +176,19 @@ def main():
             kern[k]["alg_bytes_per_launch"] = alg
             kern[k]["alg_GBps"] = alg / (kern[k]["avg_ms"] * 1e-3) / 1e9
     traffic = _traffic("flat_scatter_partition", n)
+    # whole partition: count + tile scan + scatter, per selectivity
+    per_part_s = dt / len(sels)
+    verified = None
+    if not args.only_headline:
+        # the outputs of the launch configuration timed above, once per
+        # selectivity, against the oracle's digests
+        gold = _golden()["flat_2e28_f32"]
+        for s, p in zip(sels, preds):
+            P.partition(x, p, P.MODE_PARTITION, torch.int32, out_keys=out_keys, out_idx=out_idx,
+                        split=split)
+            _verify(f"flat partition s={s}", {"keys": _sha(out_keys), "idx_i32": _sha(out_idx),
+                                              "split": int(split.item())}, gold[str(s)])
+        verified = True
     out = {
         "metric": "partitioned GElem/s + % HBM peak (flat, segmented, fwd+bwd) on 1 MI355X",
         "value": len(sels) * n / dt / 1e9,
@@ -163,8 +209,15 @@ def main():
         "roofline": {"bound": "hbm", "kernel": "flat_scatter_partition",
                      "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
-                     "alg_bytes_per_launch": scan_alg},
-        "whole_step_alg_GBps": len(sels) * (scan_alg + count_alg) / dt / 1e9,
+                     "alg_bytes_per_launch": scan_alg,
+                     # the whole partition (count, tile scan and scatter) on
+                     # its 12 algorithmic bytes per element
+                     "frac_whole_op": scan_alg / per_part_s / 1e9 / HBM_PEAK_GBPS},
+        # 12 B/element: read keys, write positions, write keys
+        "whole_step_alg_GBps": len(sels) * scan_alg / dt / 1e9,
+        # 16 B/element: the above plus the counting pass's re-read of the keys
+        "whole_step_design_GBps": len(sels) * (scan_alg + count_alg) / dt / 1e9,
+        "verified_against_oracle": verified,
         "kernels": kern,
     }
 
@@ -195,14 +248,27 @@ def sections(args, torch, np, P, W, dev, x, out_keys, out_idx, split):
     res["copy_reference"] = {"bytes": 2 * 4 * n, "ms": t * 1e3, "GBps": 8 * n / t / 1e9}
     del y
     # filter mode (single pass with decoupled look-back) on the same input
+    gold = _golden()
     fl = {}
     for s in W.FLAT_LARGE_SELECTIVITIES:
         p = P.Pred.lt(s)
+        P.profile_read()
+        P.profile_enable(True)
         t = timed(lambda: P.partition(x, p, P.MODE_FILTER, torch.int32, out_keys=out_keys,
                                       out_idx=out_idx, split=split), steps, 2, torch)
+        P.profile_enable(False)
+        k = _prof(P).get("flat_scan_filter", {})
         T = int(split.item())
         alg = n * 4 + n * 4 + T * 4
-        fl[str(s)] = {"ms": t * 1e3, "GElem_s": n / t / 1e9, "alg_GBps": alg / t / 1e9}
+        r = {"ms": t * 1e3, "GElem_s": n / t / 1e9, "alg_GBps": alg / t / 1e9,
+             "frac_of_8TBps": alg / t / 8e12, "alg_bytes": alg}
+        if k:
+            r["kernel_avg_ms"] = k["avg_ms"]
+            r["traffic"] = _traffic("flat_scan_filter", n) if s == 0.5 else None
+        r["verified_against_oracle"] = _verify(
+            f"filter s={s}", {"keys": _sha(out_keys[:T]), "idx_i32": _sha(out_idx), "split": T},
+            gold["filter_2e28_f32"][str(s)])
+        fl[str(s)] = r
     res["flat_filter_2^28_f32"] = fl
     # small flat config: n = 2^20 int32 keys, key % 2 == 0, int64 indices
     ks = torch.from_numpy(W.int_keys(W.FLAT_SMALL_N, W.FLAT_SMALL_SEED)).to(dev)
@@ -211,8 +277,11 @@ def sections(args, torch, np, P, W, dev, x, out_keys, out_idx, split):
     ois = torch.empty(ks.numel(), dtype=torch.int64, device=dev)
     t = timed(lambda: P.partition(ks, p, P.MODE_PARTITION, torch.int64, out_keys=oks,
                                   out_idx=ois, split=split), steps * 10, 5, torch)
-    res["flat_partition_2^20_int32_int64idx"] = {"ms": t * 1e3, "GElem_s": ks.numel() / t / 1e9,
-                                                 "alg_GBps": ks.numel() * 16 / t / 1e9}
+    res["flat_partition_2^20_int32_int64idx"] = {
+        "ms": t * 1e3, "GElem_s": ks.numel() / t / 1e9, "alg_GBps": ks.numel() * 16 / t / 1e9,
+        "verified_against_oracle": _verify(
+            "flat 2^20", {"keys": _sha(oks), "idx_i64": _sha(ois), "split": int(split.item())},
+            gold["flat_2e20_i32"])}
     del ks, oks, ois
     res["segmented_10^4_rows"] = section_segmented(args, torch, np, P, W, dev)
     res["fwd_bwd_2^24x16"] = section_autograd(args, torch, np, P, W, dev)
@@ -261,6 +330,17 @@ def section_segmented(args, torch, np, P, W, dev):
                 P.partition(keys[lo:hi], pred, P.MODE_PARTITION, torch.int32,
                             out_keys=ok[lo:hi], out_idx=oi[lo:hi], split=sp[k:k + 1])
     t_calls = timed(per_call, 2, 1, torch)
+    gold = _golden()["segmented_1e4_rows"]
+
+    def outputs(o):
+        return {"keys": _sha(o.out_keys), "idx_i32": _sha(o.out_idx), "seg_split": _sha(o.seg_split),
+                "flags": _sha(o.flags)}
+
+    # the eager call above wrote the graph's buffers last: replay the graph
+    # once more and check what it writes
+    g.launch()
+    torch.cuda.synchronize()
+    ok_graph = _verify("segmented graph", outputs(g), gold)
     g.close()
     # the same tiling with the other way of learning T_k of multi-item rows
     row_sync = tiling[3] if len(tiling) > 3 else P._lib.ROW_SYNC_AUTO
@@ -268,12 +348,20 @@ def section_segmented(args, torch, np, P, W, dev):
                                  else P._lib.ROW_SYNC_WAIT,)
     g2 = P.SegmentedGraph(keys, shape, pred, tune=other)
     t_other = timed(g2.launch, steps, 2, torch)
+    ok_other = _verify("segmented graph, other row sync", outputs(g2), gold)
     g2.close()
     alg = n * (4 + 4 + 4 + 1) + W.SEG_M * 16
+    main = kern.get("seg_main_partition")
+    if main:
+        main["alg_bytes_per_launch"] = n * 13
+        main["alg_GBps"] = n * 13 / (main["avg_ms"] * 1e-3) / 1e9
+        main["traffic"] = _traffic("seg_main_partition", n)
     return {"n": n, "m": W.SEG_M, "tiling": {"block": tiling[0], "rows": tiling[1],
                                              "wgs_per_cu": tiling[2],
                                              "row_sync": ["auto", "count", "nowait", "wait"][row_sync]},
+            "verified_against_oracle": ok_graph and ok_other,
             "graph_ms_other_row_sync": t_other * 1e3,
+            "other_row_sync": ["auto", "count", "nowait", "wait"][other[3]],
             "tuner_ms": tune_ms, "tiling_from_cache": cached,
             "graph_ms": t_graph * 1e3, "graph_GElem_s": n / t_graph / 1e9,
             "graph_alg_GBps": alg / t_graph / 1e9, "graph_frac_of_8TBps": alg / t_graph / 8e12,
@@ -305,6 +393,17 @@ def section_autograd(args, torch, np, P, W, dev):
     torch.cuda.synchronize()
     P.profile_enable(False)
     kern = _prof(P)
+    for k in ("scatter_rows", "gather_rows"):
+        if k in kern:
+            kern[k]["alg_bytes_per_launch"] = n * (8 + 2 * cols * 4)
+            kern[k]["alg_GBps"] = n * (8 + 2 * cols * 4) / (kern[k]["avg_ms"] * 1e-3) / 1e9
+            kern[k]["traffic"] = _traffic(k, n)
+    gold = _golden()["fwd_bwd_2e24x16"]
+    p.grad = None
+    y, _, _, _ = P.partition_scatter(keys, p, pred)
+    y.backward(gy)
+    verified = _verify("fwd+bwd", {"y": _sha(y), "grad_payload": _sha(p.grad)}, gold)
+    del y
 
     def per_call():
         _, idx, _ = P.partition(keys, pred, P.MODE_PARTITION, torch.int64, want_keys=False)
@@ -327,7 +426,7 @@ def section_autograd(args, torch, np, P, W, dev):
     t_ta = timed(torch_autograd, steps, 2, torch)
     row = cols * 4
     alg = n * (4 + 8) + n * (8 + row + row) + n * (8 + row + row)   # partition + fwd + bwd
-    return {"n": n, "row_bytes": row, "ours_ms": t_ours * 1e3, "ours_alg_GBps": alg / t_ours / 1e9,
+    return {"n": n, "row_bytes": row, "verified_against_oracle": verified, "ours_ms": t_ours * 1e3, "ours_alg_GBps": alg / t_ours / 1e9,
             "ours_frac_of_8TBps": alg / t_ours / 8e12,
             "per_call_index_copy_select_ms": t_plain * 1e3,
             "torch_autograd_index_select_ms": t_ta * 1e3,
@@ -339,30 +438,50 @@ def section_props(args, torch, np, P, W, dev):
     """int64 n = 2^28: Range+Inj+Bij on a permutation, Mono on a sorted array,
     all four on the permutation with 1000 planted faults."""
     n = W.PROPS_N
+    gold = _golden()["check_props_2e28_i64"]
     perm_np = W.permutation(n, W.PROPS_PERM_SEED)
     perm = torch.from_numpy(perm_np).to(dev)
     steps = max(3, args.steps // 2)
     out = {}
+
+    def named(v, names):
+        rows = P.verdicts(v)
+        col = {"range": 0, "mono": 1, "inj": 2, "bij": 3}
+        return {k: list(rows[col[k]]) for k in names}
+
     m3 = P.RANGE | P.INJ | P.BIJ
     t = timed(lambda: P.check_props(perm, m3, 0, n, 0, n), steps, 1, torch)
+    v = named(P.check_props(perm, m3, 0, n, 0, n), ("range", "inj", "bij"))
     out["perm_range_inj_bij"] = {"ms": t * 1e3, "GElem_s": n / t / 1e9, "alg_GBps": 8 * n / t / 1e9,
-                                 "verdicts": P.verdicts(P.check_props(perm, m3, 0, n, 0, n))[:4]}
+                                 "frac_of_8TBps": 8 * n / t / 8e12, "verdicts": v,
+                                 "verified_against_oracle": _verify("props perm", v, gold["perm"])}
     P.profile_enable(True)
     P.check_props(perm, m3, 0, n, 0, n)
     torch.cuda.synchronize()
     P.profile_enable(False)
-    out["perm_kernels"] = _prof(P)
+    kern = _prof(P)
+    for k in ("props_scan", "props_check"):
+        if k in kern:
+            kern[k]["traffic"] = _traffic(k, n)
+    out["perm_kernels"] = kern
     bad = torch.from_numpy(W.inject_faults(perm_np, 1000, 1052, "mixed")).to(dev)
     del perm_np
     m4 = m3 | P.MONO
     t = timed(lambda: P.check_props(bad, m4, 0, n, 0, n), steps, 1, torch)
-    out["faulty_all4"] = {"ms": t * 1e3, "GElem_s": n / t / 1e9,
-                          "verdicts": P.verdicts(P.check_props(bad, m4, 0, n, 0, n))[:4]}
+    v = named(P.check_props(bad, m4, 0, n, 0, n), ("range", "mono", "inj", "bij"))
+    out["faulty_all4"] = {"ms": t * 1e3, "GElem_s": n / t / 1e9, "verdicts": v,
+                          "verified_against_oracle": _verify("props faulty", v, gold["faulty_1000_mixed"])}
+    P.profile_enable(True)
+    P.check_props(bad, m4, 0, n, 0, n)
+    torch.cuda.synchronize()
+    P.profile_enable(False)
+    out["faulty_kernels"] = _prof(P)
     del bad, perm
     srt = torch.from_numpy(W.sorted_keys(n, W.PROPS_SORTED_SEED)).to(dev)
     t = timed(lambda: P.check_props(srt, P.MONO), steps, 1, torch)
+    v = named(P.check_props(srt, P.MONO), ("mono",))
     out["sorted_mono"] = {"ms": t * 1e3, "GElem_s": n / t / 1e9, "alg_GBps": 8 * n / t / 1e9,
-                          "verdicts": P.verdicts(P.check_props(srt, P.MONO))[1:2]}
+                          "verdicts": v, "verified_against_oracle": _verify("props sorted", v, gold["sorted"])}
     return out
 
 
@@ -412,6 +531,9 @@ def section_verify(args, torch, np, P, W, dev):
             assert torch.equal(dst, ref), f"{name} differs from the checked scatter"
             t = timed(fn, steps, 1, torch)
             r[name] = {"ms": t * 1e3, "GElem_s": n / t / 1e9}
+        r["verified_against_oracle"] = _verify(
+            f"verify {n}", {"keys": _sha(ref), "split": int(split.item())},
+            _golden()["verify_partition2"][f"{n // 1_000_000}M"])
         r["speedup_static"] = r["base"]["ms"] / r["static"]["ms"]
         r["speedup_static_opt"] = r["base"]["ms"] / r["static_opt"]["ms"]
         r["paper_a100_ms"] = PAPER_A100_MS[n]
@@ -489,7 +611,10 @@ def section_partition3(args, torch, np, P, W, dev, x=None):
     P.profile_enable(False)
     k = _prof(P)
     sc = k.get("flatv_scatter", {}).get("avg_ms", 0.0)
+    ok_ = _verify("partition3", {"keys": _sha(ok), "idx_i32": _sha(oi), "counts": cnt.cpu().tolist()},
+                  _golden()["partition3_2e28_f32"])
     return {"ms": t * 1e3, "GElem_s": n / t / 1e9, "counts": cnt.cpu().tolist(),
+            "verified_against_oracle": ok_,
             "scatter_alg_GBps": 12 * n / (sc * 1e-3) / 1e9 if sc else None, "kernels": k}
 
 
@@ -517,20 +642,42 @@ def section_shape_tools(args, torch, np, P, W, dev):
             "sgm_sum_2^26_int64": {"ms": t_sg * 1e3, "alg_GBps": 17 * m / t_sg / 1e9}}
 
 
+def _host_cpu():
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model
+
+
 def cpu_baseline(W, np):
     """The oracle (single-threaded C) on the first 2^27 elements of the headline
-    input, once per selectivity."""
+    input, once per selectivity, with this process pinned to one host core."""
     import oracle as O
     ns = 1 << 27
     xs = W.f32_uniform(W.FLAT_LARGE_N, W.FLAT_LARGE_SEED)[:ns].copy()
-    t0 = time.perf_counter()
-    for s in W.FLAT_LARGE_SELECTIVITIES:
-        O.partition2(xs, O.Pred.lt(s))
-    dt = time.perf_counter() - t0
+    allowed = sorted(os.sched_getaffinity(0))
+    core = allowed[0]
+    os.sched_setaffinity(0, {core})
+    try:
+        t0 = time.perf_counter()
+        for s in W.FLAT_LARGE_SELECTIVITIES:
+            O.partition2(xs, O.Pred.lt(s))
+        dt = time.perf_counter() - t0
+    finally:
+        os.sched_setaffinity(0, set(allowed))
     return {"value": len(W.FLAT_LARGE_SELECTIVITIES) * ns / dt / 1e9, "unit": "GElem/s",
             "cores": 1, "kind": "oracle",
+            "host": {"cpu_model": _host_cpu(), "os_cpu_count": os.cpu_count(),
+                     "cores_allowed": len(allowed), "pinned_core": core},
             "sample": f"partition2 of the first 2^27 of the 2^28 f32 inputs, once per "
-                      f"s in {list(W.FLAT_LARGE_SELECTIVITIES)}; {dt:.1f} s on one host core"}
+                      f"s in {list(W.FLAT_LARGE_SELECTIVITIES)}; {dt:.1f} s on one host core "
+                      f"(process pinned to core {core})"}
 
 
 if __name__ == "__main__":
