@@ -86,6 +86,10 @@ def test_bij_count_failure_reports_missing_value():
     # Img strictly inside Rcd
     both(perm, P.BIJ, 0, n, 10, n - 10)
     both(np.arange(50), P.BIJ, 0, 100, 0, 100)
+    # negative missing values (the least missing value is reduced as an
+    # offset from img_lo), global-bitmap path and chunked path
+    assert both(np.array([-3, -1, -4]), P.BIJ, -5, 0, -5, 0)[3] == (0, 3, -5)
+    both(W.permutation(1 << 17, 4) - (1 << 17) - 2, P.BIJ, -(1 << 17) - 2, 0, -(1 << 17) - 2, 0)
 
 
 def test_empty_and_tiny():
@@ -94,19 +98,72 @@ def test_empty_and_tiny():
         both(np.array(X, dtype=np.int64), ALL4, 0, 4, 0, 3, op=P.MONO_GT)
 
 
-def test_config_props_full_size():
-    """int64 n = 2^28: a permutation (Bij), a sorted array (Mono), and the
-    permutation with 1..1000 planted duplicates / out-of-range values."""
-    n = W.PROPS_N
-    perm = W.permutation(n, W.PROPS_PERM_SEED)
-    v = both(perm)
+def test_values_repeated_many_times():
+    """300 values each written to 4 more positions (5 occurrences each) of a
+    permutation with a ragged length: the single rescan must still find the
+    earliest second occurrence, whatever order the occurrences arrive in."""
+    g = np.random.default_rng(7)
+    for n in ((1 << 20) + 5, 3 * 32768 + 1):
+        x = W.permutation(n, 8)
+        src = g.choice(n, 300, replace=False)
+        for s_ in src:
+            x[g.choice(n, 4, replace=False)] = x[s_]
+        both(x)
+        both(x.astype(np.int32), dtype=np.int32)
+
+
+@pytest.mark.parametrize("n,k", [(1 << 20, 5000), (50_000, 3000)])
+def test_more_repeats_than_the_list_holds(n, k):
+    """More than 2048 repeated values: the two global fallback passes locate
+    the first violation (chunked path at 2^20, bitmap path below 2^16)."""
+    perm = W.permutation(n, 9)
+    both(W.inject_faults(perm, k, 99, "dup"))
+
+
+def test_chunked_path_int32_and_offset_rcd():
+    """Arrays of at least 2^16 take the chunked path: int32 elements, an Rcd
+    with a negative base whose width is not a multiple of the 2^20-value
+    bucket, Img strictly inside, and a chunk tail of n % 4 elements."""
+    g = np.random.default_rng(11)
+    n = 200_003
+    x = g.integers(-100, 300_000, n)
+    both(x, ALL4, -50, 290_000, -10, 280_000, P.MONO_LE, dtype=np.int32)
+    lo = -12_345
+    perm = W.permutation(3_000_001, 12)[:n] + lo
+    both(perm, ALL4, lo, lo + 3_000_001, lo + 5, lo + 3_000_001)
+    p2 = W.permutation(n, 13)
+    both(p2, ALL4, -7, n + 1_000_000, -7, n + 1_000_000, dtype=np.int32)
+
+
+def test_chunked_path_4096_buckets():
+    """Rcd = [0, 2^32): 4096 buckets, values spread over all of them, a few
+    planted repeats; Bij fails on the count and reports the least missing."""
+    g = np.random.default_rng(14)
+    n = 1 << 20
+    x = g.choice(1 << 32, n, replace=False).astype(np.int64)
+    both(x, P.RANGE | P.INJ | P.BIJ, 0, 1 << 32)
+    x[g.choice(n, 10, replace=False)] = x[g.choice(n, 10, replace=False)]
+    both(x, P.RANGE | P.INJ | P.BIJ, 0, 1 << 32)
+
+
+@pytest.fixture(scope="module")
+def perm_2e28():
+    return W.permutation(W.PROPS_N, W.PROPS_PERM_SEED)
+
+
+def test_config_props_full_size(perm_2e28):
+    """int64 n = 2^28: a permutation (Bij) and a sorted array (Mono)."""
+    v = both(perm_2e28)
     assert v[3][0] == 1
-    for k in (1, 1000):
-        both(W.inject_faults(perm, k, 52 + k, "mixed"))
-    del perm
-    s = W.sorted_keys(n, W.PROPS_SORTED_SEED)
+    s = W.sorted_keys(W.PROPS_N, W.PROPS_SORTED_SEED)
     assert both(s, P.MONO)[1][0] == 1
     both(W.adjacent_swaps(s, 10, 70), P.MONO)
+
+
+@pytest.mark.parametrize("k", [1, 10, 100, 1000])
+def test_config_props_full_size_faults(perm_2e28, k):
+    """The 2^28 permutation with k planted duplicates / out-of-range values."""
+    both(W.inject_faults(perm_2e28, k, 52 + k, "mixed"))
 
 
 # ------------------------------------------------------------------ FiltPart
@@ -193,6 +250,9 @@ def test_bucketed_and_fallback_paths():
     y = g.integers(0, 1 << 33, 1 << 16)
     y[900] = y[800]
     both(y, P.INJ | P.RANGE, 0, 1 << 33)
+    # more than 2^22 entries per 2^20-value bucket on average: global bitmap
+    w = g.integers(0, 1 << 20, (1 << 23) + 5)
+    both(w, ALL4, 0, 1 << 20, 0, 1 << 20)
     # a bucket boundary: values just around multiples of 2^20
     z = (np.arange(n) // 7) * (1 << 20) + (np.arange(n) % 7) - 3
     both(z, P.INJ | P.RANGE, -3, int(z.max()) + 1)
