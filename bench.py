@@ -116,6 +116,10 @@ def main():
                     help="headline steps only (for profiler runs)")
     ap.add_argument("--with-copy", action="store_true",
                     help="also run one plain device copy of the input (counter calibration)")
+    ap.add_argument("--profile", default=None,
+                    choices=["flat", "filter", "segmented", "fwd_bwd", "props", "props_faulty"],
+                    help="run only this workload's launches, once untimed and --steps times, "
+                         "for rocprofv3 kernel traces and counters; prints one line")
     ap.add_argument("--section", default=None,
                     help="run only this section (segmented, autograd, props, verify, pairs, "
                          "partition3, shape_tools) and print it")
@@ -133,6 +137,9 @@ def main():
     import workloads as W
 
     dev = torch.device("cuda:0")
+    if args.profile:
+        profile_run(args, torch, np, P, W, dev)
+        return
     if args.section:
         fn = {"segmented": section_segmented, "autograd": section_autograd,
               "props": section_props, "verify": section_verify, "pairs": section_pairs,
@@ -393,10 +400,11 @@ def section_autograd(args, torch, np, P, W, dev):
     torch.cuda.synchronize()
     P.profile_enable(False)
     kern = _prof(P)
+    ib = 4 if n < (1 << 31) else 8   # index width the differentiable partition uses
     for k in ("scatter_rows", "gather_rows"):
         if k in kern:
-            kern[k]["alg_bytes_per_launch"] = n * (8 + 2 * cols * 4)
-            kern[k]["alg_GBps"] = n * (8 + 2 * cols * 4) / (kern[k]["avg_ms"] * 1e-3) / 1e9
+            kern[k]["alg_bytes_per_launch"] = n * (ib + 2 * cols * 4)
+            kern[k]["alg_GBps"] = n * (ib + 2 * cols * 4) / (kern[k]["avg_ms"] * 1e-3) / 1e9
             kern[k]["traffic"] = _traffic(k, n)
     gold = _golden()["fwd_bwd_2e24x16"]
     p.grad = None
@@ -425,7 +433,8 @@ def section_autograd(args, torch, np, P, W, dev):
 
     t_ta = timed(torch_autograd, steps, 2, torch)
     row = cols * 4
-    alg = n * (4 + 8) + n * (8 + row + row) + n * (8 + row + row)   # partition + fwd + bwd
+    # partition (read keys, write indices and partitioned keys) + fwd + bwd
+    alg = n * (4 + ib + 4) + n * (ib + row + row) + n * (ib + row + row)
     return {"n": n, "row_bytes": row, "verified_against_oracle": verified, "ours_ms": t_ours * 1e3, "ours_alg_GBps": alg / t_ours / 1e9,
             "ours_frac_of_8TBps": alg / t_ours / 8e12,
             "per_call_index_copy_select_ms": t_plain * 1e3,
@@ -640,6 +649,65 @@ def section_shape_tools(args, torch, np, P, W, dev):
     return {"mk_ii_int32": {"n": n, "ms": t_ii * 1e3, "alg_GBps": 4 * n / t_ii / 1e9},
             "mk_sgm_descr_int64": {"n": n, "ms": t_descr * 1e3, "alg_GBps": 8 * n / t_descr / 1e9},
             "sgm_sum_2^26_int64": {"ms": t_sg * 1e3, "alg_GBps": 17 * m / t_sg / 1e9}}
+
+
+def profile_run(args, torch, np, P, W, dev):
+    """One workload's launches only (inputs built first, outside the loop):
+    for rocprofv3, whose per-kernel summaries and counters are taken from
+    these runs.  A plain device copy of 1 GiB runs once first, to calibrate
+    FETCH_SIZE / WRITE_SIZE against known bytes."""
+    cal = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    torch.empty_like(cal).copy_(cal)
+    del cal
+    name = args.profile
+    if name in ("flat", "filter"):
+        x = torch.from_numpy(W.f32_uniform(W.FLAT_LARGE_N, W.FLAT_LARGE_SEED)).to(dev)
+        ok = torch.empty_like(x)
+        oi = torch.empty(x.numel(), dtype=torch.int32, device=dev)
+        sp = torch.empty(1, dtype=torch.int64, device=dev)
+        mode = P.MODE_PARTITION if name == "flat" else P.MODE_FILTER
+        preds = [P.Pred.lt(s) for s in W.FLAT_LARGE_SELECTIVITIES] if name == "flat" else [P.Pred.lt(0.5)]
+
+        def fn():
+            for p in preds:
+                P.partition(x, p, mode, torch.int32, out_keys=ok, out_idx=oi, split=sp)
+    elif name == "segmented":
+        shape_np = W.segment_sizes(W.SEG_M, W.SEG_SIZES_SEED)
+        keys = torch.from_numpy(W.int_keys(int(shape_np.sum()), W.SEG_KEYS_SEED)).to(dev)
+        shape = torch.from_numpy(shape_np).to(dev)
+        pred = P.Pred.mod_eq(3, 0)
+        g = P.SegmentedGraph(keys, shape, pred, tune=(256, 4, 64, P._lib.ROW_SYNC_WAIT))
+        fn = g.launch
+    elif name == "fwd_bwd":
+        n, cols = W.AUTOGRAD_N, W.AUTOGRAD_ROW
+        keys = torch.from_numpy(W.int_keys(n, W.AUTOGRAD_SEEDS[0])).to(dev)
+        p = torch.from_numpy(W.f32_normal((n, cols), W.AUTOGRAD_SEEDS[1])).to(dev).requires_grad_(True)
+        gy = torch.from_numpy(W.f32_normal((n, cols), W.AUTOGRAD_SEEDS[2])).to(dev)
+        pred = P.Pred.mod_eq(2, 0)
+
+        def fn():
+            p.grad = None
+            y, _, _, _ = P.partition_scatter(keys, p, pred)
+            y.backward(gy)
+    else:
+        n = W.PROPS_N
+        perm = W.permutation(n, W.PROPS_PERM_SEED)
+        if name == "props_faulty":
+            perm = W.inject_faults(perm, 1000, 1052, "mixed")
+        x = torch.from_numpy(perm).to(dev)
+        del perm
+        mask = P.RANGE | P.INJ | P.BIJ | (P.MONO if name == "props_faulty" else 0)
+
+        def fn():
+            P.check_props(x, mask, 0, n, 0, n)
+    fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        fn()
+    torch.cuda.synchronize()
+    print(json.dumps({"profile": name, "steps": args.steps,
+                      "ms_per_step": (time.perf_counter() - t0) / args.steps * 1e3}))
 
 
 def _host_cpu():

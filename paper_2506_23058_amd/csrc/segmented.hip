@@ -15,9 +15,12 @@
 // that loads stay vector loads: item j of row k covers
 //   [A_k + j*TILE, A_k + (j+1)*TILE) ∩ [o_k, o_k + s_k),   A_k = o_k rounded down to 4.
 // Kernels (all stream-ordered, capturable in one HIP graph):
-//   seg_setup -- one workgroup: validates the shape, scans it into row offsets
-//                and item offsets;
-//   seg_items -- item descriptors, written in parallel over items;
+//   seg_shape -- (up to 16384 rows) row offsets, item offsets and item
+//                descriptors in one launch: each workgroup rescans the sizes
+//                before its rows; the last one validates the shape;
+//   seg_setup, seg_items -- (more rows) the same in two launches: one
+//                workgroup scans the shape, then the descriptors are written
+//                in parallel over items;
 //   seg_count -- one wave per 1024-element chunk counts the trues of the items
 //                whose row spans several items and is not synchronised in
 //                seg_main (partition), or of every item (filter), into a
@@ -195,7 +198,7 @@ __global__ __launch_bounds__(kSetupThreads) void seg_setup_kernel(SegArgs a) {
 // One workgroup per 256 rows: the rows' offsets go to LDS, then the
 // workgroup's threads write the rows' item descriptors in parallel (an item
 // finds its row by binary search in LDS), so a row of many items costs no
-// more than many rows of one item.  Empty rows get T_k = 0 here.
+// more than many rows of one item.  (T_k of empty rows is written by seg_count.)
 __global__ __launch_bounds__(256) void seg_items_kernel(SegArgs a) {
     __shared__ int64_t s_off[257], s_it[257];
     __shared__ unsigned long long s_counted;
@@ -214,8 +217,6 @@ __global__ __launch_bounds__(256) void seg_items_kernel(SegArgs a) {
         s_it[j] = a.item_off[r0 + j];
     }
     __syncthreads();
-    if (static_cast<int>(threadIdx.x) < nr && s_it[threadIdx.x] == s_it[threadIdx.x + 1] && a.seg_split)
-        a.seg_split[r0 + threadIdx.x] = 0;   // empty row
     for (int64_t idx = s_it[0] + threadIdx.x; idx < s_it[nr]; idx += blockDim.x) {
         int lo = 0, hi = nr - 1;   // last row j with s_it[j] <= idx
         while (lo < hi) {
@@ -247,6 +248,140 @@ __global__ __launch_bounds__(256) void seg_items_kernel(SegArgs a) {
     if (threadIdx.x == 0 && s_counted) atomicAdd(a.num_counted, s_counted);
 }
 
+// Fused shape scan and item records, for up to kShapeFusedRows rows (one
+// launch instead of seg_setup + seg_items).  Workgroup j owns rows
+// [256 j, 256 j + 256) and recomputes the scan of every row before and
+// including its own (at most kShapeFusedRows sizes, read from L2), so no
+// workgroup waits for another and no state carries over between calls.  The
+// last workgroup scans all rows: it validates the shape and writes the totals,
+// the item count and the number of items the counting pass will count.  It
+// writes no output: T_k of empty rows is written by the counting kernel, once
+// the shape is known good.
+constexpr int kShapeThreads = 1024;
+constexpr int64_t kShapeFusedRows = 16384;          // sizes staged in 128 KiB of LDS
+
+__global__ __launch_bounds__(kShapeThreads) void seg_shape_kernel(SegArgs a) {
+    __shared__ int64_t lds_a[16], lds_b[16];
+    __shared__ int64_t s_off[257], s_it[257];
+    __shared__ int64_t sz[kShapeFusedRows];   // the sizes of rows [0, rend)
+    __shared__ int bad;
+    const int tid = threadIdx.x;
+    const int64_t r0 = static_cast<int64_t>(blockIdx.x) * 256;
+    const int64_t rend = a.m - r0 < 256 ? a.m : r0 + 256;   // rows [0, rend) are scanned
+    const int nr = static_cast<int>(rend - r0);
+    const bool last = rend == a.m;
+    if (tid == 0) bad = 0;
+    {   // clear the item scan's ticket and look-back descriptors
+        const int64_t g = static_cast<int64_t>(blockIdx.x) * kShapeThreads + tid;
+        const int64_t nd = (a.max_items + kScanChunk - 1) / kScanChunk;
+        for (int64_t j = g; j < nd; j += static_cast<int64_t>(gridDim.x) * kShapeThreads) a.scan_desc[j] = 0;
+        if (g == 0) *a.scan_ticket = 0;
+    }
+    __syncthreads();
+    // coalesced loads into LDS, all in flight at once; a negative size marks
+    // the shape bad and counts 0
+    {
+        constexpr int kLoads = kShapeFusedRows / kShapeThreads;
+        int64_t v[kLoads];
+#pragma unroll
+        for (int j = 0; j < kLoads; ++j) {
+            const int64_t k = tid + static_cast<int64_t>(j) * kShapeThreads;
+            v[j] = k < rend ? a.shape[k] : 0;
+        }
+#pragma unroll
+        for (int j = 0; j < kLoads; ++j) {
+            const int64_t k = tid + static_cast<int64_t>(j) * kShapeThreads;
+            if (v[j] < 0) atomicOr(&bad, 1);
+            if (k < rend) sz[k] = v[j] < 0 ? 0 : v[j];
+        }
+    }
+    __syncthreads();
+    // thread t holds rows [t per, t per + per) of [0, rend)
+    const int per = static_cast<int>((rend + kShapeThreads - 1) / kShapeThreads);
+    const int64_t k0 = static_cast<int64_t>(tid) * per;
+    const int64_t k1 = k0 + per < rend ? k0 + per : rend;
+    int64_t sum_s = 0;
+    for (int64_t k = k0; k < k1; ++k) sum_s += sz[k];
+    int64_t tot_s;
+    const int64_t off0 = block_exclusive_scan_1024(sum_s, lds_a, &tot_s);
+    // items per row depend on the row offset (4-alignment of its start)
+    auto items_of = [&](int64_t o, int64_t sk) {
+        return sk > 0 ? ((o + sk - (o & ~int64_t{3}) + a.tile - 1) >> a.tile_shift) : int64_t{0};
+    };
+    int64_t sum_it = 0, counted = 0;
+    {
+        int64_t o = off0;
+        for (int64_t k = k0; k < k1; ++k) {
+            const int64_t nit = items_of(o, sz[k]);
+            sum_it += nit;
+            const bool sib = a.mode == IXP_MODE_PARTITION && a.row_sync != IXP_ROW_SYNC_COUNT && nit > 1 &&
+                             nit <= kSibMax;
+            if (a.mode != IXP_MODE_PARTITION || (nit > 1 && !sib)) counted += nit;
+            o += sz[k];
+        }
+    }
+    int64_t tot_it;
+    const int64_t it0 = block_exclusive_scan_1024(sum_it, lds_b, &tot_it);
+    {
+        int64_t o = off0, it = it0;
+        for (int64_t k = k0; k < k1; ++k) {
+            if (k >= r0) {
+                s_off[k - r0] = o;
+                s_it[k - r0] = it;
+                a.offsets[k] = o;
+                a.item_off[k] = it;
+            }
+            it += items_of(o, sz[k]);
+            o += sz[k];
+        }
+    }
+    if (tid == 0) {
+        s_off[nr] = tot_s;
+        s_it[nr] = tot_it;
+    }
+    if (last) {
+        int64_t tot_counted;
+        (void)block_exclusive_scan_1024(counted, lds_a, &tot_counted);
+        if (tid == 0) {
+            const bool ok = !bad && tot_s == a.n && tot_it <= a.max_items;
+            a.offsets[a.m] = tot_s;
+            a.item_off[a.m] = tot_it;
+            *a.num_items = ok ? tot_it : 0;
+            *a.num_counted = ok ? static_cast<unsigned long long>(tot_counted) : 0ull;
+            *a.err = ok ? 0 : kErrShape;
+        }
+    }
+    __syncthreads();
+    // this workgroup's item records (a bad shape may ask for more than fit:
+    // those are not written, and the last workgroup reports the error)
+    for (int64_t idx = s_it[0] + tid; idx < s_it[nr] && idx < a.max_items; idx += kShapeThreads) {
+        int lo = 0, hi = nr - 1;   // last row j with s_it[j] <= idx
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_it[mid] <= idx) lo = mid;
+            else hi = mid - 1;
+        }
+        const int64_t o = s_off[lo], e = s_off[lo + 1];
+        const int64_t i0 = s_it[lo], i1 = s_it[lo + 1];
+        const int64_t q = idx - i0;
+        const int64_t ak = o & ~int64_t{3};
+        const int64_t nit = i1 - i0;
+        const bool sib = a.mode == IXP_MODE_PARTITION && a.row_sync != IXP_ROW_SYNC_COUNT && nit > 1 &&
+                         nit <= kSibMax;
+        SegItem d;
+        d.base = ak + q * a.tile;
+        d.lo = d.base > o ? d.base : o;
+        d.hi = d.base + a.tile < e ? d.base + a.tile : e;
+        d.tbase = sib ? o : 0;
+        d.fbase = 0;
+        d.row = static_cast<int32_t>(r0 + lo);
+        d.kind = (nit == 1 ? 1 : 0) | (q == 0 ? 2 : 0) | (sib ? 4 | static_cast<int32_t>(nit << 8) : 0);
+        d.first = sib ? i0 : 0;
+        a.items[idx] = d;
+        a.counts[idx] = 0;
+    }
+}
+
 // ------------------------------------------------------------------ count --
 // One wave per 1024-element chunk of a counted item (items of rows that span
 // several items in partition mode, every item in filter mode); each wave adds
@@ -257,6 +392,13 @@ __global__ __launch_bounds__(256) void seg_count_kernel(SegArgs a, Pred pred) {
     using WT = Tile<kWave, IXP_SEG_COUNT_ROWS, 4>;   // one wave, 256 * rows elements
     constexpr int kCLog = kSegCountLog;
     const int lane = threadIdx.x & (kWave - 1);
+    if (*a.err != 0) return;   // a bad shape: no output is written
+    if (a.seg_split) {
+        // T_k = 0 for empty rows (rows without items), once the shape is known good
+        for (int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; k < a.m;
+             k += static_cast<int64_t>(gridDim.x) * blockDim.x)
+            if (a.item_off[k] == a.item_off[k + 1]) a.seg_split[k] = 0;
+    }
     if (*a.num_counted == 0) return;   // every item is counted in seg_main
     const int64_t nitems = *a.num_items;
     const int cshift = a.tile_shift > kCLog ? a.tile_shift - kCLog : 0;   // log2(chunks per item)
@@ -584,11 +726,23 @@ __global__ __launch_bounds__(256) void seg_fill_kernel(SegArgs a, Out *out, cons
     }
 }
 
+// Row offsets, item offsets and item records: one fused launch for up to
+// kShapeFusedRows rows, else the one-workgroup scan and the item writer.
+int launch_shape(const SegArgs &a, hipStream_t st) {
+    const uint32_t rblocks = static_cast<uint32_t>(ceil_div(a.m > 0 ? a.m : 1, 256));
+    if (a.m <= kShapeFusedRows) {
+        IXP_LAUNCH("seg_shape", seg_shape_kernel, dim3(rblocks), dim3(kShapeThreads), 0, st, a);
+        return launch_status();
+    }
+    IXP_LAUNCH("seg_setup", seg_setup_kernel, dim3(1), dim3(kSetupThreads), 0, st, a);
+    if (launch_status() != IXP_OK) return IXP_EHIP;
+    IXP_LAUNCH("seg_items", seg_items_kernel, dim3(rblocks), dim3(256), 0, st, a);
+    return launch_status();
+}
+
 template <int TOOL, class Out>
 int launch_tool(const SegArgs &a, Out *out, const int64_t *xs, hipStream_t st) {
-    IXP_LAUNCH("seg_setup", seg_setup_kernel, dim3(1), dim3(kSetupThreads), 0, st, a);
-    const uint32_t rblocks = static_cast<uint32_t>(ceil_div(a.m > 0 ? a.m : 1, 256));
-    IXP_LAUNCH("seg_items", seg_items_kernel, dim3(rblocks), dim3(256), 0, st, a);
+    if (launch_shape(a, st) != IXP_OK) return IXP_EHIP;
     const int64_t cap = static_cast<int64_t>(device_cus()) * 16;
     const int64_t grid = a.max_items < cap ? (a.max_items > 0 ? a.max_items : 1) : cap;
     IXP_LAUNCH(TOOL == 0 ? "seg_mk_ii" : "seg_mk_sgm_descr", (seg_fill_kernel<TOOL, Out>),
@@ -673,11 +827,7 @@ int launch_main(const SegArgs &a, const Pred &p, const SegGeom &g, int mode, int
 
 template <class Pred>
 int launch_all(const SegArgs &a, const Pred &p, const SegGeom &g, int mode, int idx_t, hipStream_t st) {
-    IXP_LAUNCH("seg_setup", seg_setup_kernel, dim3(1), dim3(kSetupThreads), 0, st, a);
-    if (launch_status() != IXP_OK) return IXP_EHIP;
-    const uint32_t rblocks = static_cast<uint32_t>(ceil_div(a.m > 0 ? a.m : 1, 256));
-    IXP_LAUNCH("seg_items", seg_items_kernel, dim3(rblocks), dim3(256), 0, st, a);
-    if (launch_status() != IXP_OK) return IXP_EHIP;
+    if (launch_shape(a, st) != IXP_OK) return IXP_EHIP;
     const int cus = device_cus();
     // one wave per chunk of the largest possible item list, capped
     const int64_t chunk_waves = a.max_items * (a.tile > (1 << kSegCountLog) ? a.tile >> kSegCountLog : 1);

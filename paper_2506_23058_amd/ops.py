@@ -601,9 +601,9 @@ class PartitionScatter(torch.autograd.Function):
     """Differentiable partition of a payload carried by its keys.
 
     forward(keys, payload, pred, mode): the partition2 indices of ``keys``
-    (int64, from the HIP partition) move every payload row to its partitioned
-    position with the atomic-free row scatter; returns
-    (y, partitioned keys, indices, split).  In FILTER mode y holds the kept rows
+    (from the HIP partition; int32 when n < 2^31, else int64) move every
+    payload row to its partitioned position with the atomic-free row scatter;
+    returns (y, partitioned keys, indices, split).  In FILTER mode y holds the kept rows
     first (its remaining rows are zero).
     backward: the indices are a bijection onto [0, n) (PARTITION) or an
     injection into [0, split) (FILTER), so the gradient of a row is the
@@ -613,7 +613,9 @@ class PartitionScatter(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, keys, payload, pred, mode=L.MODE_PARTITION):
-        ok, idx, split = partition(keys, pred, mode, torch.int64)
+        # narrower indices move fewer bytes in both directions
+        idx_dtype = torch.int32 if keys.numel() < (1 << 31) else torch.int64
+        ok, idx, split = partition(keys, pred, mode, idx_dtype)
         y = torch.zeros_like(payload) if mode == L.MODE_FILTER else torch.empty_like(payload)
         scatter_inj(y, idx, payload)
         ctx.save_for_backward(idx)

@@ -20,7 +20,8 @@ DEV = "cuda:0"
 
 
 @pytest.mark.parametrize("cols,dtype", [(16, torch.float32), (3, torch.float32), (8, torch.float64),
-                                        (1, torch.int32)])
+                                        (1, torch.int32), (4, torch.float32), (8, torch.float32),
+                                        (32, torch.float32), (64, torch.float32), (128, torch.float32)])
 @pytest.mark.parametrize("idx_dtype", [torch.int32, torch.int64])
 def test_scatter_and_gather_rows_match_oracle(cols, dtype, idx_dtype):
     n = 100_003
@@ -72,8 +73,8 @@ def test_partition_scatter_forward_and_gradient_exact(n):
     # torch reference: y = payload[inv] with inv the inverse permutation; its
     # gradient accumulates gy into zeros through inv (one contribution per
     # row), which equals ours in value -- only a -0.0 in gy comes back +0.0
-    inv = torch.empty_like(idx)
-    inv[idx] = torch.arange(n, device=DEV)
+    inv = torch.empty(n, dtype=torch.int64, device=DEV)
+    inv[idx.long()] = torch.arange(n, device=DEV)
     pr = torch.from_numpy(payload).to(DEV).requires_grad_(True)
     yr = pr.index_select(0, inv)
     assert torch.equal(yr.detach(), y)
@@ -83,11 +84,14 @@ def test_partition_scatter_forward_and_gradient_exact(n):
     assert (grad[differ] == 0).all()
 
 
-def test_finite_differences_float64():
-    """L = sum(w * y) in float64.  The map is a permutation of rows, so central
-    differences reproduce <grad, dv> up to float64 summation error, where dv is
-    the perturbation actually applied after rounding to f32."""
-    n, cols = 1 << 16, W.AUTOGRAD_ROW
+@pytest.mark.parametrize("n", [1 << 16, W.AUTOGRAD_N])
+def test_finite_differences_float64(n):
+    """L = sum(w * y) in float64, at 2^16 rows and at the workload's 2^24.  The
+    map is a permutation of rows, so central differences reproduce <grad, dv>
+    up to float64 summation error, where dv is the perturbation actually
+    applied after rounding to f32."""
+    print(f"[fd] n={n}", flush=True)
+    cols = W.AUTOGRAD_ROW
     keys = torch.from_numpy(W.int_keys(n, 43)).to(DEV)
     p = torch.from_numpy(W.f32_normal((n, cols), 44)).to(DEV)
     w = torch.from_numpy(W.f32_normal((n, cols), 45)).to(DEV).double()
