@@ -117,7 +117,7 @@ def main():
     ap.add_argument("--with-copy", action="store_true",
                     help="also run one plain device copy of the input (counter calibration)")
     ap.add_argument("--profile", default=None,
-                    choices=["flat", "filter", "segmented", "fwd_bwd", "props", "props_faulty"],
+                    choices=["flat", "filter", "flat_small", "segmented", "fwd_bwd", "props", "props_faulty"],
                     help="run only this workload's launches, once untimed and --steps times, "
                          "for rocprofv3 kernel traces and counters; prints one line")
     ap.add_argument("--section", default=None,
@@ -671,6 +671,15 @@ def profile_run(args, torch, np, P, W, dev):
         def fn():
             for p in preds:
                 P.partition(x, p, mode, torch.int32, out_keys=ok, out_idx=oi, split=sp)
+    elif name == "flat_small":
+        ks = torch.from_numpy(W.int_keys(W.FLAT_SMALL_N, W.FLAT_SMALL_SEED)).to(dev)
+        oks = torch.empty_like(ks)
+        ois = torch.empty(ks.numel(), dtype=torch.int64, device=dev)
+        sp = torch.empty(1, dtype=torch.int64, device=dev)
+        p = P.Pred.mod_eq(2, 0)
+
+        def fn():
+            P.partition(ks, p, P.MODE_PARTITION, torch.int64, out_keys=oks, out_idx=ois, split=sp)
     elif name == "segmented":
         shape_np = W.segment_sizes(W.SEG_M, W.SEG_SIZES_SEED)
         keys = torch.from_numpy(W.int_keys(int(shape_np.sum()), W.SEG_KEYS_SEED)).to(dev)

@@ -55,6 +55,12 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
            static_cast<uint32_t>(__builtin_amdgcn_readlane(iv, 48));
 }
 
+__device__ __forceinline__ int64_t wave_sum_i64(int64_t v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
 __device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int lane) {
     const uint32_t lo = static_cast<uint32_t>(
         __builtin_amdgcn_readlane(static_cast<int>(static_cast<uint32_t>(v)), lane));

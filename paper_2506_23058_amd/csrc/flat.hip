@@ -21,12 +21,16 @@
 //                mbcnt, the tile prefix by one load; indices written in input
 //                order with vector stores, keys staged in LDS in output order
 //                and written as the tile's two contiguous runs.
+// Up to 1024 tiles (n <= 2^22) skip the tile scan: one workgroup counts each
+// tile (a wave per 1024 elements), and each scatter workgroup adds up the tile
+// counts before its tile and in total itself.
 // Filter (single pass, two kernels):
 //   init      -- clears the tile descriptors, ticket and error word;
 //   scan      -- tiles taken in ticket order; each publishes its count, finds
 //                its prefix by decoupled look-back over the descriptors,
 //                publishes its inclusive prefix, then writes as above.  The
 //                last tile writes T.
+#include <atomic>
 #include <mutex>
 
 #include "device.hpp"
@@ -87,6 +91,13 @@ struct FlatArgs {
     int32_t need_keys;
 };
 
+// A partition of at most this many tiles skips the one-workgroup tile scan:
+// one workgroup counts each tile (a wave per kSmallChunk elements), and every
+// scatter workgroup adds up the tile counts itself (4 words per thread) and
+// tile 0 writes T.
+constexpr int64_t kSmallTiles = 1024;
+constexpr int64_t kSmallChunk = 1024;
+
 // Counting waves per partition call (fixed, so the workspace size does not
 // depend on the device).
 constexpr int64_t kCountWaves = 8192;
@@ -138,6 +149,34 @@ __global__ __launch_bounds__(256) void flat_count_kernel(FlatArgs a, Pred pred) 
     if (lane == 0 && w < kCountWaves) a.wsum[w] = static_cast<int64_t>(run);
 }
 
+// Small partitions: workgroup t counts tile t, one wave per kSmallChunk
+// elements, and writes the tile's count to wsum[t].
+template <int VEC, class Pred>
+__global__ __launch_bounds__(256) void flat_count_small_kernel(FlatArgs a, Pred pred) {
+    using WT = Tile<kWave, kSmallChunk / (kWave * VEC), VEC>;
+    constexpr int kTile = FlatCfg<IXP_MODE_PARTITION, VEC>::kTile;
+    static_assert(WT::kSize == kSmallChunk && kTile == 4 * kSmallChunk, "one chunk per wave");
+    __shared__ uint32_t wc[4];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = wave_id();
+    const int64_t t = blockIdx.x;
+    const int64_t tlo = t * kTile;
+    const int64_t thi = tlo + kTile < a.n ? tlo + kTile : a.n;
+    const int64_t lo = tlo + static_cast<int64_t>(wave) * kSmallChunk;
+    uint32_t cnt = 0;
+    if (lo < thi) {   // wave-uniform
+        // [lo, thi) bounds the valid positions; the chunk itself covers
+        // [lo, lo + kSmallChunk).  (Passing min(thi, lo + kSmallChunk) here
+        // made hipcc select the bound on a stale SCC after a VCC compare.)
+        WT chunk;
+        chunk.load(a.keys, a.n, lo, lo, thi, pred, !Pred::kUsesFlags, 0, lane);
+        cnt = chunk.wave_count();
+    }
+    if (lane == 0) wc[wave] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) a.wsum[t] = static_cast<int64_t>(wc[0]) + wc[1] + wc[2] + wc[3];
+}
+
 // One workgroup of 1024 threads turns wsum[0..nw) (nw <= 8 * 1024) from run
 // totals into exclusive prefixes, in place, and writes T.  Thread i holds the
 // 8 consecutive entries [8i, 8i+8) in registers; the thread sums are scanned
@@ -186,16 +225,24 @@ __global__ __launch_bounds__(1024) void flat_tile_scan_kernel(int64_t *wsum, int
     }
 }
 
-template <int VEC, class Pred, int MODE, class Idx>
+// Partition paths (PATH):
+//   0  the tile prefix and T come from the counting kernel and the tile scan;
+//   1  at most kSmallTiles tiles, counted by flat_count_small (one
+//      workgroup per tile, one wave per 1024 elements): every workgroup adds
+//      up the tile counts before its own and in total itself, and tile 0
+//      writes T.
+template <int VEC, class Pred, int MODE, class Idx, int PATH = 0>
 __global__ __launch_bounds__((FlatCfg<MODE, VEC>::kBlock)) void flat_scan_kernel(FlatArgs a, Pred pred) {
     using Cfg = FlatCfg<MODE, VEC>;
     using T = typename Cfg::T;
     constexpr int kTile = T::kSize;
     constexpr int kRows = Cfg::kRows;
     constexpr int kBlock = Cfg::kBlock;
+    static_assert(PATH == 0 || MODE == IXP_MODE_PARTITION, "small paths are partitions");
     __shared__ uint32_t stage[kTile];
     __shared__ uint32_t wtot[T::kWaves];
     __shared__ int64_t sh[2];
+    __shared__ int64_t sh_small[PATH > 0 ? T::kWaves : 1][2];
 
     const int tid = threadIdx.x;
     const int wave = wave_id();
@@ -203,7 +250,7 @@ __global__ __launch_bounds__((FlatCfg<MODE, VEC>::kBlock)) void flat_scan_kernel
     int64_t t;
     if (MODE == IXP_MODE_PARTITION) {
 #if IXP_XCD_MAP
-        t = xcd_tile(blockIdx.x, a.num_tiles);
+        t = PATH > 0 ? blockIdx.x : xcd_tile(blockIdx.x, a.num_tiles);
 #else
         t = blockIdx.x;
 #endif
@@ -214,9 +261,9 @@ __global__ __launch_bounds__((FlatCfg<MODE, VEC>::kBlock)) void flat_scan_kernel
     }
     const int64_t lo = t * kTile;
     const int64_t hi = lo + kTile < a.n ? lo + kTile : a.n;
-    // partition: the tile prefix and T are ready before the kernel starts
+    // path 0: the tile prefix and T are ready before the kernel starts
     int64_t excl = 0, total = 0;
-    if (MODE == IXP_MODE_PARTITION) {
+    if (MODE == IXP_MODE_PARTITION && PATH == 0) {
         excl = static_cast<int64_t>(a.desc[t]) + a.wsum[t / a.tiles_per_wave];
         total = *a.split;
     }
@@ -225,6 +272,34 @@ __global__ __launch_bounds__((FlatCfg<MODE, VEC>::kBlock)) void flat_scan_kernel
     tile.load(a.keys, a.n, lo, lo, hi, pred, a.need_keys != 0, wave, lane);
     tile.wave_ranks();
     const uint32_t tcount = tile.block_ranks(wtot, wave, lane);
+
+    if constexpr (PATH > 0) {
+        // wsum[j] is tile j's count
+        constexpr int kPer = (kSmallTiles + kBlock - 1) / kBlock;
+        int64_t before = 0, all = 0;
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const int64_t j = static_cast<int64_t>(tid) * kPer + k;
+            const int64_t c = j < a.num_tiles ? a.wsum[j] : 0;
+            all += c;
+            before += j < t ? c : 0;
+        }
+        before = wave_sum_i64(before);
+        all = wave_sum_i64(all);
+        if (lane == 0) {
+            sh_small[wave][0] = before;
+            sh_small[wave][1] = all;
+        }
+        __syncthreads();
+        for (int w = 0; w < T::kWaves; ++w) {
+            excl += sh_small[w][0];
+            total += sh_small[w][1];
+        }
+        if (t == 0 && tid == 0) {
+            *a.split = total;
+            *a.err = 0;
+        }
+    }
 
     if (MODE == IXP_MODE_FILTER) {
         if (tid == 0 && t > 0) desc_store(a.desc + t, kStA | tcount);
@@ -293,23 +368,38 @@ int launch_flat(FlatArgs a, const Pred &pred, int mode, int idx_t, hipStream_t s
         a.num_tiles = ceil_div(n, Cfg::kTile);
         const int64_t nt = a.num_tiles;
         int64_t nw = 0;
-        if (nt > 0) {
+        const bool small = nt > 0 && nt <= kSmallTiles;
+        if (small) {
+            IXP_LAUNCH("flat_count", (flat_count_small_kernel<VEC, Pred>), dim3(static_cast<uint32_t>(nt)),
+                       dim3(256), 0, st, a, pred);
+        } else if (nt > 0) {
             a.tiles_per_wave = ceil_div(nt, kCountWaves);
             nw = ceil_div(nt, a.tiles_per_wave);
             IXP_LAUNCH("flat_count", (flat_count_kernel<VEC, Pred>),
                        dim3(static_cast<uint32_t>(ceil_div(nw, 4))), dim3(256), 0, st, a, pred);
         }
-        IXP_LAUNCH("flat_tile_scan", flat_tile_scan_kernel, dim3(1), dim3(1024), 0, st, a.wsum, nw,
-                   a.split, a.err);
+        if (!small)
+            IXP_LAUNCH("flat_tile_scan", flat_tile_scan_kernel, dim3(1), dim3(1024), 0, st, a.wsum, nw,
+                       a.split, a.err);
         if (nt == 0) return launch_status();
         // at most kScatterWgsPerCu scatter workgroups per CU (LDS reserved at launch)
         const size_t cap = VEC == 4 ? lds_for_wgs_per_cu(kScatterWgsPerCu, Cfg::kTile * 4 + 256) : 0;
-        if (idx_t == IXP_I32)
+        if (small) {
+            if (idx_t == IXP_I32)
+                IXP_LAUNCH("flat_scatter_partition",
+                           (flat_scan_kernel<VEC, Pred, IXP_MODE_PARTITION, int32_t, 1>),
+                           dim3(static_cast<uint32_t>(nt)), dim3(Cfg::kBlock), 0, st, a, pred);
+            else
+                IXP_LAUNCH("flat_scatter_partition",
+                           (flat_scan_kernel<VEC, Pred, IXP_MODE_PARTITION, int64_t, 1>),
+                           dim3(static_cast<uint32_t>(nt)), dim3(Cfg::kBlock), 0, st, a, pred);
+        } else if (idx_t == IXP_I32) {
             IXP_LAUNCH("flat_scatter_partition", (flat_scan_kernel<VEC, Pred, IXP_MODE_PARTITION, int32_t>),
                        dim3(static_cast<uint32_t>(nt)), dim3(Cfg::kBlock), cap, st, a, pred);
-        else
+        } else {
             IXP_LAUNCH("flat_scatter_partition", (flat_scan_kernel<VEC, Pred, IXP_MODE_PARTITION, int64_t>),
                        dim3(static_cast<uint32_t>(nt)), dim3(Cfg::kBlock), cap, st, a, pred);
+        }
     } else {
         using Cfg = FlatCfg<IXP_MODE_FILTER, VEC>;
         a.num_tiles = ceil_div(n, Cfg::kTile);
