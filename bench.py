@@ -42,6 +42,7 @@ KERNEL_SOURCES = {
     "gather_rows": ("rows.hip", "device.hpp", "host.hpp"),
     "props_scan": ("props.hip", "device.hpp", "host.hpp"),
     "props_check": ("props.hip", "device.hpp", "host.hpp"),
+    "props_rescan": ("props.hip", "device.hpp", "host.hpp"),
 }
 
 DIGESTS = os.path.join(ROOT, "tests", "golden", "bench_digests.json")
@@ -484,7 +485,10 @@ def section_props(args, torch, np, P, W, dev):
     P.check_props(bad, m4, 0, n, 0, n)
     torch.cuda.synchronize()
     P.profile_enable(False)
-    out["faulty_kernels"] = _prof(P)
+    fk = _prof(P)
+    if "props_rescan" in fk:
+        fk["props_rescan"]["traffic"] = _traffic("props_rescan", n)
+    out["faulty_kernels"] = fk
     del bad, perm
     srt = torch.from_numpy(W.sorted_keys(n, W.PROPS_SORTED_SEED)).to(dev)
     t = timed(lambda: P.check_props(srt, P.MONO), steps, 1, torch)
