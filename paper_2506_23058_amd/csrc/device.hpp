@@ -287,19 +287,21 @@ __device__ __forceinline__ void stream_store(T *p, T v) {
 // the contiguous run [base + w*ROWS*64*VEC, +ROWS*64*VEC); inside it row r,
 // lane l holds elements base + w*ROWS*64*VEC + r*64*VEC + l*VEC + q, q < VEC.
 // Only positions in [lo, hi) are valid; invalid ones are never stored.
-template <int BLOCK, int ROWS, int VEC>
+// Bits holds one flag bit per element of a thread; a 32-bit word (enough for
+// ROWS * VEC <= 32) keeps the flag arithmetic in single registers.
+template <int BLOCK, int ROWS, int VEC, class Bits = uint64_t>
 struct Tile {
     static constexpr int kWaves = BLOCK / kWave;
     static constexpr int kPerWave = ROWS * kWave * VEC;
     static constexpr int kSize = BLOCK * ROWS * VEC;
     static_assert(BLOCK % kWave == 0 && BLOCK <= 1024, "block");
     static_assert(VEC == 1 || VEC == 4, "vec");
-    static_assert(ROWS * VEC <= 64, "flag bits");
+    static_assert(ROWS * VEC <= 8 * static_cast<int>(sizeof(Bits)), "flag bits");
 
     uint32_t key[ROWS][VEC];
     uint32_t rank[ROWS][VEC];   // exclusive rank among the tile's trues
-    uint64_t fbits = 0;         // bit r*VEC+q: element is valid and true
-    uint64_t vbits = 0;         // bit r*VEC+q: element is valid
+    Bits fbits = 0;             // bit r*VEC+q: element is valid and true
+    Bits vbits = 0;             // bit r*VEC+q: element is valid
     uint32_t wave_total = 0;    // trues of this wave (uniform)
 
     __device__ static __forceinline__ int64_t pos(int64_t base, int wave, int r, int lane, int q) {
@@ -376,17 +378,19 @@ struct Tile {
         // validity from 32-bit offsets relative to lo (a tile spans < 2^31)
         const int32_t l0 = static_cast<int32_t>(base - lo) + wave * kPerWave + lane * VEC;
         const uint32_t span = static_cast<uint32_t>(hi - lo);
+        // The words are built by shifting in one bit per element, last
+        // element first: a per-element mask constant would hold a register of
+        // its own (a select with a literal has no encoding here), and every
+        // predicate is plain arithmetic, so no branch guards it.
 #pragma unroll
-        for (int r = 0; r < ROWS; ++r) {
-#pragma unroll
-            for (int q = 0; q < VEC; ++q) {
-                const int32_t l = l0 + r * (kWave * VEC) + q;
-                const bool valid = static_cast<uint32_t>(l) < span;
-                key[r][q] = kv[r][q];
-                const bool f = valid && pred(kv[r][q], fv[r][q]);
-                vbits |= static_cast<uint64_t>(valid) << (r * VEC + q);
-                fbits |= static_cast<uint64_t>(f) << (r * VEC + q);
-            }
+        for (int k = ROWS * VEC - 1; k >= 0; --k) {
+            const int r = k / VEC, q = k % VEC;
+            const int32_t l = l0 + r * (kWave * VEC) + q;
+            const bool valid = static_cast<uint32_t>(l) < span;
+            key[r][q] = kv[r][q];
+            const bool f = valid & pred(kv[r][q], fv[r][q]);
+            vbits = (vbits << 1) | static_cast<Bits>(valid);
+            fbits = (fbits << 1) | static_cast<Bits>(f);
         }
         (void)n;
     }
@@ -397,8 +401,8 @@ struct Tile {
         return w0 < hi && w0 + kPerWave > lo;
     }
 
-    __device__ __forceinline__ bool flag(int r, int q) const { return (fbits >> (r * VEC + q)) & 1ull; }
-    __device__ __forceinline__ bool valid(int r, int q) const { return (vbits >> (r * VEC + q)) & 1ull; }
+    __device__ __forceinline__ bool flag(int r, int q) const { return (fbits >> (r * VEC + q)) & 1u; }
+    __device__ __forceinline__ bool valid(int r, int q) const { return (vbits >> (r * VEC + q)) & 1u; }
 
     // Ranks of the trues inside this wave's run, from one ballot per
     // (row, q): the rank of element (r, lane, q) counts the trues of earlier

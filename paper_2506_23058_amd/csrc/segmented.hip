@@ -566,12 +566,22 @@ __device__ __forceinline__ void row_counts(const SegArgs &a, const Pred &pred, i
 
 // Workgroups take items round-robin (item = blockIdx.x + k * gridDim.x: no
 // shared queue counter, whose serialised atomics would cost ~10 ns per
-// item); a grid smaller than the item count makes them persistent.  Wave 0 prefetches the next item's 48-byte descriptor,
-// one 8-byte word per lane, while the workgroup processes the current one.
+// item); a grid smaller than the item count makes them persistent.  Wave 0
+// prefetches the next item's 48-byte descriptor, one 8-byte word per lane,
+// while the workgroup processes the current one.
+//
+// Each wave owns the LDS run of its own elements: right after ranking them it
+// places its keys there, trues first, then falses, each in input order.  The
+// keys then leave the registers before the workgroup's count exchange, and
+// after it the wave writes its two runs straight to their places in the
+// output (its trues follow the trues of the waves before it, its falses the
+// falses before it).  No other wave reads that LDS run, so it needs no
+// barrier of its own; the one at the top of the loop separates items.
 template <int BLOCK, int ROWS, class Pred, int MODE, class Idx>
 __global__ __launch_bounds__(BLOCK) void seg_main_kernel(SegArgs a, Pred pred) {
-    using T = Tile<BLOCK, ROWS, 4>;
+    using T = Tile<BLOCK, ROWS, 4, uint32_t>;
     constexpr int kTile = T::kSize;
+    constexpr int kPerWave = T::kPerWave;
     constexpr int kWords = sizeof(SegItem) / 8;
     static_assert(sizeof(SegItem) % 8 == 0 && kWords <= kWave, "descriptor words");
     __shared__ uint32_t stage[kTile];
@@ -586,6 +596,7 @@ __global__ __launch_bounds__(BLOCK) void seg_main_kernel(SegArgs a, Pred pred) {
     const int64_t nitems = *a.num_items;
     Idx *out_idx = static_cast<Idx *>(a.out_idx);
     const int64_t *words = reinterpret_cast<const int64_t *>(a.items);
+    uint32_t *wstage = stage + wave * kPerWave;
 
     int64_t next = blockIdx.x, next_word = 0;
     auto prefetch = [&]() {
@@ -619,12 +630,77 @@ __global__ __launch_bounds__(BLOCK) void seg_main_kernel(SegArgs a, Pred pred) {
             prefetch();
         }
         const int64_t lo = d.lo, hi = d.hi, base = d.base;
+        const int32_t span = static_cast<int32_t>(hi - lo);
+        // offsets from lo (a tile spans < 2^31): the wave's first element,
+        // where its valid elements start, and how many there are
+        const int32_t wl0 = static_cast<int32_t>(base - lo) + wave * kPerWave;
+        const int32_t vbeg = wl0 < 0 ? 0 : (wl0 < span ? wl0 : span);
+        const int32_t wl1 = wl0 + kPerWave;
+        const int32_t vend = wl1 < 0 ? 0 : (wl1 < span ? wl1 : span);
+        const uint32_t wvalid = static_cast<uint32_t>(vend - vbeg);
 
         T tile;
-        if (T::wave_live(base, lo, hi, wave))   // waves past a short item load nothing
+        const bool live = T::wave_live(base, lo, hi, wave);   // waves past a short item load nothing
+        if (live) {
             tile.load(a.keys, a.n, base, lo, hi, pred.at_row(d.row), a.need_keys != 0, wave, lane);
-        tile.wave_ranks();
-        const uint32_t tcount = tile.block_ranks(wtot, wave, lane);
+        } else {
+            // defined keys on every path: an undefined value here would keep
+            // the last item's keys in registers across the whole loop
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) tile.key[r][q] = 0;
+        }
+
+        // rowpre[r]: trues of this wave before this lane's group of row r
+        uint32_t rowpre[ROWS];
+        uint32_t wt = 0;   // trues of this wave (uniform)
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r) {
+            uint32_t below = 0, row_total = 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint64_t m = ballot(tile.flag(r, q));
+                below += rank_below(m);
+                row_total += static_cast<uint32_t>(__builtin_popcountll(m));
+            }
+            rowpre[r] = wt + below;
+            wt += row_total;
+        }
+        // rank of element (r, q) among the wave's trues (for a false: trues before it)
+        auto wrank = [&](int r, int q) -> uint32_t {
+            const uint32_t g = (tile.fbits >> (4 * r)) & ((1u << q) - 1u);
+            return rowpre[r] + static_cast<uint32_t>(__builtin_popcount(g));
+        };
+        const int32_t l0 = wl0 + lane * 4;   // offset from lo of (row 0, q 0)
+
+        if (a.out_keys && live) {
+            // Every element is written, without a branch: a valid one at its
+            // place in the run (falses too in filter mode, where they are
+            // never read), an invalid one at lw mod kPerWave.  lw counts from
+            // the wave's first valid element, so the invalid elements fill
+            // exactly the slots past the valid ones, one each.
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const uint32_t rw = wrank(r, q);
+                    const uint32_t lw = static_cast<uint32_t>(l0 + r * (kWave * 4) + q - vbeg);
+                    const uint32_t at = tile.flag(r, q) ? rw : wt + (lw - rw);
+                    wstage[tile.valid(r, q) ? at : (lw & (kPerWave - 1))] = tile.key[r][q];
+                }
+            }
+        }
+
+        if (lane == 0) wtot[wave] = wt;
+        __syncthreads();
+        uint32_t tbefore = 0, tcount = 0;   // trues of the waves before this one; of the tile
+#pragma unroll
+        for (int w = 0; w < T::kWaves; ++w) {
+            const uint32_t v = wtot[w];
+            tbefore += w < wave ? v : 0u;
+            tcount += v;
+        }
 
         int64_t tbase = d.tbase, fbase = d.fbase;
         if (MODE == IXP_MODE_PARTITION && (d.kind & 1)) {
@@ -642,51 +718,57 @@ __global__ __launch_bounds__(BLOCK) void seg_main_kernel(SegArgs a, Pred pred) {
         }
         const bool first = (d.kind & 2) != 0;
 
-        const int32_t l0 = static_cast<int32_t>(base - lo) + wave * T::kPerWave + lane * 4;
+        if (out_idx || a.flags_out) {
+            // Opaque copies of the flag words: every per-element bit and rank
+            // below is recomputed from them, where the compiler would
+            // otherwise keep the staging's sixteen of each in registers
+            // through the exchange.
+            uint32_t fb = tile.fbits, vb = tile.vbits;
+            asm volatile("" : "+v"(fb), "+v"(vb));
 #pragma unroll
-        for (int r = 0; r < ROWS; ++r) {
-            const int64_t p0 = T::pos(base, wave, r, lane, 0);
-            Idx v[4];
-            uint32_t vm = 0;
-            uint32_t fl = 0;
+            for (int r = 0; r < ROWS; ++r) {
+                const int64_t p0 = T::pos(base, wave, r, lane, 0);
+                const int32_t lr = l0 + r * (kWave * 4);   // offset from lo of q = 0
+                const uint32_t fr = (fb >> (4 * r)) & 0xFu;
+                const uint32_t vm = (vb >> (4 * r)) & 0xFu;
+                // the descriptor byte 1 sits at l == 0, i.e. at q = -lr
+                const uint32_t fl = (first && lr <= 0 && lr > -4) ? 1u << (8 * -lr) : 0u;
+                Idx v[4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const uint32_t rt = tile.rank[r][q];
-                const int32_t l = l0 + r * (kWave * 4) + q;   // offset from lo
-                const uint32_t rf = static_cast<uint32_t>(l) - rt;
-                const bool f = tile.flag(r, q);
-                const bool ok = tile.valid(r, q);
-                vm |= static_cast<uint32_t>(ok) << q;
-                fl |= static_cast<uint32_t>(first && l == 0) << (8 * q);
-                if (MODE == IXP_MODE_PARTITION)
-                    v[q] = static_cast<Idx>(f ? tbase + rt : fbase + rf);
-                else
-                    v[q] = static_cast<Idx>(f ? tbase + rt : -1);
-                if (a.out_keys && ok && (MODE == IXP_MODE_PARTITION || f))
-                    stage[f ? rt : tcount + rf] = tile.key[r][q];
-            }
-            if (vm) {
-                if (out_idx) store_idx_group<4, Idx>(out_idx, p0, v, vm);
-                if (a.flags_out) {
-                    if (vm == 0xFu) {
-                        stream_store(reinterpret_cast<uint32_t *>(a.flags_out + p0), fl);
-                    } else {
+                for (int q = 0; q < 4; ++q) {
+                    const int32_t l = lr + q;
+                    const uint32_t rt = tbefore + rowpre[r] +   // rank among the tile's trues
+                                        static_cast<uint32_t>(__builtin_popcount(fr & ((1u << q) - 1u)));
+                    const uint32_t rf = static_cast<uint32_t>(l) - rt;
+                    const bool f = (fr >> q) & 1u;
+                    if (MODE == IXP_MODE_PARTITION)
+                        v[q] = static_cast<Idx>(f ? tbase + rt : fbase + rf);
+                    else
+                        v[q] = static_cast<Idx>(f ? tbase + rt : -1);
+                }
+                if (vm) {
+                    if (out_idx) store_idx_group<4, Idx>(out_idx, p0, v, vm);
+                    if (a.flags_out) {
+                        if (vm == 0xFu) {
+                            stream_store(reinterpret_cast<uint32_t *>(a.flags_out + p0), fl);
+                        } else {
 #pragma unroll
-                        for (int q = 0; q < 4; ++q)
-                            if ((vm >> q) & 1u)
-                                a.flags_out[p0 + q] = static_cast<uint8_t>(fl >> (8 * q));
+                            for (int q = 0; q < 4; ++q)
+                                if ((vm >> q) & 1u)
+                                    a.flags_out[p0 + q] = static_cast<uint8_t>(fl >> (8 * q));
+                        }
                     }
                 }
             }
         }
         if (a.out_keys) {
-            __syncthreads();
-            const uint32_t nvalid = static_cast<uint32_t>(hi - lo);
-            write_run<BLOCK>(stage, 0, tcount, tbase, a.out_keys, a.n, tid);
-            if (MODE == IXP_MODE_PARTITION)
-                write_run<BLOCK>(stage, tcount, nvalid - tcount, fbase, a.out_keys, a.n, tid);
+            // this wave's own LDS run, written by this wave before the exchange
+            write_run<kWave>(wstage, 0, wt, tbase + tbefore, a.out_keys, a.n, lane);
+            if (MODE == IXP_MODE_PARTITION) {
+                const uint32_t fbefore = static_cast<uint32_t>(vbeg) - tbefore;   // falses before this wave
+                write_run<kWave>(wstage, wt, wvalid - wt, fbase + fbefore, a.out_keys, a.n, lane);
+            }
         }
-        __syncthreads();   // LDS is reused by the next item
     }
 }
 
