@@ -528,7 +528,7 @@ __device__ __forceinline__ void row_counts(const SegArgs &a, const Pred &pred, i
         while (missing && !nowait && polls > 0) {
             --polls;
             __builtin_amdgcn_s_sleep(1);
-            if ((missing >> lane) & 1ull) w = desc_load(cnt + d.first + j);
+            if (mine && !(w & kCntReady)) w = desc_load(cnt + d.first + j);   // this lane's bit of `missing`
             missing = ballot(mine && !(w & kCntReady));
         }
         while (missing) {
@@ -600,7 +600,7 @@ __global__ __launch_bounds__(BLOCK) void seg_main_kernel(SegArgs a, Pred pred) {
 
     int64_t next = blockIdx.x, next_word = 0;
     auto prefetch = [&]() {
-        if (lane < kWords && next < nitems) next_word = words[next * kWords + lane];
+        if (lane < kWords && next < nitems) next_word = (words + next * kWords)[static_cast<uint32_t>(lane)];
     };
     if (wave == 0) prefetch();
 

@@ -6,6 +6,7 @@ current HIP stream, and check the returned status.  All computation happens in
 the library's HIP kernels.
 """
 import ctypes
+import functools
 from dataclasses import dataclass
 from typing import Optional
 
@@ -53,17 +54,31 @@ class Pred:
         return Pred(L.PRED_MOD_ROW, d=int(d))
 
     def c(self) -> L.ixp_pred:
+        """The C struct, built once per predicate and device pointers (the
+        library copies it during the call)."""
+        ptrs = (self.flags.data_ptr() if self.flags is not None else None,
+                self.row_s.data_ptr() if self.row_s is not None else None)
+        cached = self.__dict__.get("_c")
+        if cached is not None and cached[0] == ptrs:
+            return cached[1]
         p = L.ixp_pred()
         p.kind = self.kind
         p.d = self.d
         p.r = self.r
         p.s = self.s
-        p.flags = self.flags.data_ptr() if self.flags is not None else None
-        p.row_s = self.row_s.data_ptr() if self.row_s is not None else None
+        p.flags, p.row_s = ptrs
+        object.__setattr__(self, "_c", (ptrs, p))   # a cache, not a field
         return p
 
 
+_raw_stream = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+
+
 def _stream_ptr(device) -> int:
+    """The current HIP stream of `device`, as a raw pointer."""
+    if _raw_stream is not None:
+        idx = device.index if isinstance(device, torch.device) else device
+        return _raw_stream(torch.cuda.current_device() if idx is None else idx)
     return torch.cuda.current_stream(device).cuda_stream
 
 
@@ -74,10 +89,16 @@ def _ptr(t: Optional[torch.Tensor]):
 _ws_cache = {}
 
 
+def _ws_key(device, tag: str):
+    if not isinstance(device, torch.device):
+        device = torch.device(device)
+    return (device.type, device.index, tag)
+
+
 def workspace(nbytes: int, device, tag: str = "default") -> torch.Tensor:
     """A cached device workspace of at least ``nbytes`` bytes (one per tag and
     device; calls that share a tag must not overlap on different streams)."""
-    key = (str(device), tag)
+    key = _ws_key(device, tag)
     buf = _ws_cache.get(key)
     if buf is None or buf.numel() < nbytes:
         buf = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
@@ -89,6 +110,11 @@ def _check_dev(*ts):
     for t in ts:
         if t is not None and not t.is_cuda:
             raise ValueError("tensors must live on a GPU")
+
+
+@functools.lru_cache(maxsize=256)
+def _partition_ws_bytes(n: int) -> int:
+    return L.lib().ixp_partition_workspace(n)
 
 
 def partition(keys: torch.Tensor, pred: Pred, mode: int = L.MODE_PARTITION,
@@ -111,7 +137,7 @@ def partition(keys: torch.Tensor, pred: Pred, mode: int = L.MODE_PARTITION,
         out_idx = torch.empty(n, dtype=idx_dtype, device=dev)
     if split is None:
         split = torch.empty(1, dtype=torch.int64, device=dev)
-    ws = workspace(L.lib().ixp_partition_workspace(n), dev, "partition")
+    ws = workspace(_partition_ws_bytes(n), dev, "partition")
     pc = pred.c()
     rc = L.lib().ixp_partition(
         _ptr(keys), _KEY_T[keys.dtype], n, ctypes.byref(pc), mode,
@@ -308,14 +334,14 @@ def sgm_sum(flags: torch.Tensor, xs: torch.Tensor, out: Optional[torch.Tensor] =
 
 def shape_tools_error(ws_tag: str = "shape_tools", device="cuda:0") -> int:
     """Blocking: the error recorded by the last mk_ii / mk_sgm_descr call."""
-    ws = _ws_cache.get((str(torch.device(device)), ws_tag))
+    ws = _ws_cache.get(_ws_key(device, ws_tag))
     return 0 if ws is None else L.lib().ixp_read_error(_ptr(ws), _stream_ptr(ws.device))
 
 
 def segmented_error(ws_tag: str = "segmented", device="cuda:0") -> int:
     """Blocking: status recorded by the last segmented call on this workspace
     (IXP_EINVAL for an invalid shape array), then cleared."""
-    ws = _ws_cache.get((str(torch.device(device)), ws_tag))
+    ws = _ws_cache.get(_ws_key(device, ws_tag))
     if ws is None:
         return L.IXP_OK
     return L.lib().ixp_read_error(_ptr(ws), _stream_ptr(ws.device))
