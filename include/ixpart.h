@@ -229,6 +229,9 @@ size_t ixp_segmented_workspace(int64_t n, int64_t m, const ixp_tuning *tune);
  *   d_flags_out (nullable, device u8[n]) = the segment descriptor: 1 at the
  *              first element of every non-empty row, 0 elsewhere (mkSgmDescr
  *              applied to a row of ones, Section 2.1).
+ * out_keys, out_idx, d_seg_split and d_flags_out may each be NULL (not
+ * produced); keys may be NULL when the predicate is IXP_PRED_FLAGS and
+ * out_keys is NULL.
  * A negative size or a size sum different from n is detected on the device:
  * the call then writes no output and ixp_read_error() on the same workspace
  * reports IXP_EINVAL.  Enqueues 6 kernels (shape scan, item records, counts

@@ -284,3 +284,59 @@ def test_filter_seg_counts_beyond_2e32():
     assert rc == 0
     assert P._lib.lib().ixp_read_error(ws.data_ptr(), torch.cuda.current_stream().cuda_stream) == 0
     assert seg.cpu().tolist() == shape.cpu().tolist()
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("tune", [(256, 4, 64, 3), (256, 8, 64, 3), (512, 2, 0, 1)])
+def test_any_subset_of_outputs_through_the_c_abi(mode, tune):
+    """Every output of the C ABI may be NULL.  Each subset is produced on its
+    own and compared with the oracle: keys only, indices only, descriptor
+    bytes only, split points only, and indices of a flag predicate with no
+    key array at all.  Rows of 0 to ~3 tiles, so single-item rows, exchanging
+    multi-item rows and empty rows all occur."""
+    g = np.random.default_rng(11 + mode)
+    shape = g.integers(0, 3 * 4096, 900).astype(np.int64)
+    shape[g.integers(0, 900, 120)] = 0
+    shape[::97] = 1
+    n = int(shape.sum())
+    keys = W.int_keys(n, 12)
+    flags = (g.random(n) < 0.4).astype(np.uint8)
+    lib = P._lib.lib()
+    t = P._lib.ixp_tuning()
+    t.block, t.rows, t.wgs_per_cu, t.row_sync = tune
+    m = len(shape)
+    ws = torch.empty(lib.ixp_segmented_workspace(n, m, ctypes.byref(t)), dtype=torch.uint8, device=DEV)
+    kt = torch.from_numpy(keys).to(DEV)
+    st = torch.from_numpy(shape).to(DEV)
+    stream = torch.cuda.current_stream().cuda_stream
+    for kind in ("mod", "flags"):
+        gp, op = _preds(kind, d=3, r=1, flags=flags)
+        pc = gp.c()
+        ys, idx, seg, fl = O.partition2L(keys, shape, op, mode)
+        nout = n if mode == P.MODE_PARTITION else int(seg.sum())
+        for want in ("keys", "idx", "flags", "split", "idx_no_keys"):
+            if want == "idx_no_keys" and kind != "flags":
+                continue
+            print(f"[seg-subset] mode={mode} tune={tune} pred={kind} out={want}", flush=True)
+            ok = torch.full((n,), 0x7F7F7F7F, dtype=torch.int32, device=DEV) if want == "keys" else None
+            oi = torch.full((n,), -7, dtype=torch.int64, device=DEV) if want.startswith("idx") else None
+            of = torch.full((n,), 9, dtype=torch.uint8, device=DEV) if want == "flags" else None
+            osp = torch.full((m,), -5, dtype=torch.int64, device=DEV) if want == "split" else None
+            src = None if want == "idx_no_keys" else kt.data_ptr()
+            rc = lib.ixp_segmented_partition(
+                src, P._lib.I32, n, st.data_ptr(), m, ctypes.byref(pc), mode,
+                ok.data_ptr() if ok is not None else None, oi.data_ptr() if oi is not None else None,
+                P._lib.I64, osp.data_ptr() if osp is not None else None,
+                of.data_ptr() if of is not None else None, ctypes.byref(t), ws.data_ptr(), ws.numel(), stream)
+            assert rc == 0
+            assert lib.ixp_read_error(ws.data_ptr(), stream) == 0
+            if ok is not None:
+                got = ok.cpu().numpy()
+                assert np.array_equal(got[:nout].view(np.uint32), ys[:nout].view(np.uint32))
+                assert (got[nout:] == 0x7F7F7F7F).all()
+            if oi is not None:
+                assert np.array_equal(oi.cpu().numpy(), idx)
+            if of is not None:
+                assert np.array_equal(of.cpu().numpy(), fl)
+            if osp is not None:
+                assert np.array_equal(osp.cpu().numpy(), seg)
