@@ -268,21 +268,28 @@ __global__ __launch_bounds__((FlatCfg<MODE, VEC>::kBlock)) void flat_scan_kernel
         total = *a.split;
     }
 
+    // small path: wsum[j] is tile j's count; each thread's share of the
+    // counts is loaded before the tile, so the two loads overlap
+    constexpr int kPer = PATH > 0 ? (kSmallTiles + kBlock - 1) / kBlock : 1;
+    int64_t cnt[kPer];
+    if constexpr (PATH > 0) {
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const int64_t j = static_cast<int64_t>(tid) * kPer + k;
+            cnt[k] = j < a.num_tiles ? a.wsum[j] : 0;
+        }
+    }
+
     T tile;
     tile.load(a.keys, a.n, lo, lo, hi, pred, a.need_keys != 0, wave, lane);
     tile.wave_ranks();
-    const uint32_t tcount = tile.block_ranks(wtot, wave, lane);
-
     if constexpr (PATH > 0) {
-        // wsum[j] is tile j's count
-        constexpr int kPer = (kSmallTiles + kBlock - 1) / kBlock;
         int64_t before = 0, all = 0;
 #pragma unroll
         for (int k = 0; k < kPer; ++k) {
             const int64_t j = static_cast<int64_t>(tid) * kPer + k;
-            const int64_t c = j < a.num_tiles ? a.wsum[j] : 0;
-            all += c;
-            before += j < t ? c : 0;
+            all += cnt[k];
+            before += j < t ? cnt[k] : 0;
         }
         before = wave_sum_i64(before);
         all = wave_sum_i64(all);
@@ -290,7 +297,11 @@ __global__ __launch_bounds__((FlatCfg<MODE, VEC>::kBlock)) void flat_scan_kernel
             sh_small[wave][0] = before;
             sh_small[wave][1] = all;
         }
-        __syncthreads();
+    }
+    // (its barrier also publishes sh_small)
+    const uint32_t tcount = tile.block_ranks(wtot, wave, lane);
+
+    if constexpr (PATH > 0) {
         for (int w = 0; w < T::kWaves; ++w) {
             excl += sh_small[w][0];
             total += sh_small[w][1];

@@ -115,6 +115,38 @@ def test_invalid_arguments_rejected():
         P.partition(kt, P.Pred.mod_eq(2, 0), mode=7)
 
 
+@pytest.mark.parametrize("n", [1023, 1024, 1025, 2047, 3 * 1024 + 3, (1 << 20) - 1, 1 << 20,
+                               (1 << 20) + 1, (1 << 22) - 1, 1 << 22, (1 << 22) + 1])
+@pytest.mark.parametrize("idx_dtype", [torch.int32, torch.int64])
+def test_sizes_at_the_small_path_bounds(n, idx_dtype):
+    """One wave per 1024-element tile up to 2^20 keys, 4096-element tiles
+    counted per tile up to 2^22, the counting pass above: every side of both
+    bounds, with a key predicate and with a flag predicate."""
+    keys = W.int_keys(n, 17)
+    run_both(keys, "mod", P.MODE_PARTITION, idx_dtype, d=3, r=2)
+    flags = (np.random.default_rng(n).random(n) < 0.3).astype(np.uint8)
+    run_both(keys, "flags", P.MODE_PARTITION, idx_dtype, flags=flags)
+
+
+def test_flag_predicate_without_keys_small():
+    """A flag predicate needs no key array when no keys are written."""
+    n = 300_001
+    flags = (np.random.default_rng(3).random(n) < 0.6).astype(np.uint8)
+    _, idx, t = O.partition2(np.zeros(n, dtype=np.int32), O.Pred.from_flags(flags))
+    ft = torch.from_numpy(flags).to(DEV)
+    oi = torch.empty(n, dtype=torch.int64, device=DEV)
+    sp = torch.empty(1, dtype=torch.int64, device=DEV)
+    lib = P._lib.lib()
+    ws = torch.empty(lib.ixp_partition_workspace(n), dtype=torch.uint8, device=DEV)
+    pc = P.Pred.from_flags(ft).c()
+    import ctypes
+    rc = lib.ixp_partition(None, P._lib.I32, n, ctypes.byref(pc), P.MODE_PARTITION, None, oi.data_ptr(),
+                           P._lib.I64, sp.data_ptr(), ws.data_ptr(), ws.numel(),
+                           torch.cuda.current_stream().cuda_stream)
+    assert rc == 0
+    assert int(sp.item()) == t and np.array_equal(oi.cpu().numpy(), idx)
+
+
 def test_config_flat_small_int64_indices():
     """n = 2^20 int32 keys uniform in [0, 2^31), key % 2 == 0, int64 indices."""
     keys = W.int_keys(W.FLAT_SMALL_N, W.FLAT_SMALL_SEED)
