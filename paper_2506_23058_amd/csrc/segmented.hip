@@ -101,6 +101,18 @@ int64_t seg_max_items(int64_t n, int64_t m, int64_t tile) {
     return ceil_div(n + 3 * m, tile) + m + 1;
 }
 
+// Rows are cut into items of `tile` elements from the 16-byte group holding
+// the row's first element, which fixes the row's item count.  The first item
+// starts one 128-byte line earlier when that keeps the count: then every
+// boundary between two items of the row falls on a cache line, and the items
+// (written by different workgroups, often on different XCDs with their own
+// L2) share no output line inside the row.  Only row ends remain mid-line.
+__device__ __forceinline__ int64_t row_first_base(int64_t o, int64_t sk, int64_t nit, int64_t tile,
+                                                  int32_t shift) {
+    const int64_t line = o & ~int64_t{31};
+    return ((o + sk - line + tile - 1) >> shift) == nit ? line : (o & ~int64_t{3});
+}
+
 // ------------------------------------------------------------------ setup --
 // One workgroup of 1024 threads.  Shapes are processed in chunks of 4096 rows
 // (4 consecutive rows per thread); the per-thread sums of row sizes and item
@@ -227,8 +239,8 @@ __global__ __launch_bounds__(256) void seg_items_kernel(SegArgs a) {
         const int64_t o = s_off[lo], e = s_off[lo + 1];
         const int64_t i0 = s_it[lo], i1 = s_it[lo + 1];
         const int64_t q = idx - i0;
-        const int64_t ak = o & ~int64_t{3};
         const int64_t nit = i1 - i0;
+        const int64_t ak = row_first_base(o, e - o, nit, a.tile, a.tile_shift);
         const bool sib = a.mode == IXP_MODE_PARTITION && a.row_sync != IXP_ROW_SYNC_COUNT && nit > 1 &&
                          nit <= kSibMax;
         SegItem d;
@@ -364,8 +376,8 @@ __global__ __launch_bounds__(kShapeThreads) void seg_shape_kernel(SegArgs a) {
         const int64_t o = s_off[lo], e = s_off[lo + 1];
         const int64_t i0 = s_it[lo], i1 = s_it[lo + 1];
         const int64_t q = idx - i0;
-        const int64_t ak = o & ~int64_t{3};
         const int64_t nit = i1 - i0;
+        const int64_t ak = row_first_base(o, e - o, nit, a.tile, a.tile_shift);
         const bool sib = a.mode == IXP_MODE_PARTITION && a.row_sync != IXP_ROW_SYNC_COUNT && nit > 1 &&
                          nit <= kSibMax;
         SegItem d;
