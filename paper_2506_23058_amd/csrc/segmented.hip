@@ -925,8 +925,8 @@ int launch_all(const SegArgs &a, const Pred &p, const SegGeom &g, int mode, int 
     const int cus = device_cus();
     // one wave per chunk of the largest possible item list, capped
     const int64_t chunk_waves = a.max_items * (a.tile > (1 << kSegCountLog) ? a.tile >> kSegCountLog : 1);
-    const int64_t cblocks = ceil_div(chunk_waves, 4) < static_cast<int64_t>(cus) * 64
-                                ? ceil_div(chunk_waves, 4) : static_cast<int64_t>(cus) * 64;
+    const int64_t cblocks = ceil_div(chunk_waves, 4) < static_cast<int64_t>(cus) * 16
+                                ? ceil_div(chunk_waves, 4) : static_cast<int64_t>(cus) * 16;
     IXP_LAUNCH("seg_count", (seg_count_kernel<Pred>), dim3(static_cast<uint32_t>(cblocks)), dim3(256), 0,
                st, a, p);
     IXP_LAUNCH("seg_scan_items", seg_scan_items_kernel,
