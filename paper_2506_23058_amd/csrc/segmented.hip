@@ -13,7 +13,9 @@
 // Work decomposition.  Each non-empty row is cut into work items of at most
 // one tile (TILE = block * rows * 4 elements), aligned to 4-element groups so
 // that loads stay vector loads: item j of row k covers
-//   [A_k + j*TILE, A_k + (j+1)*TILE) ∩ [o_k, o_k + s_k),   A_k = o_k rounded down to 4.
+//   [A_k + j*TILE, A_k + (j+1)*TILE) ∩ [o_k, o_k + s_k),
+// A_k = o_k rounded down to 32 (a 128-byte line) when that gives the row no
+// more items than rounding down to 4, else o_k rounded down to 4.
 // Kernels (all stream-ordered, capturable in one HIP graph):
 //   seg_shape -- (up to 16384 rows) row offsets, item offsets and item
 //                descriptors in one launch: each workgroup rescans the sizes
@@ -32,11 +34,10 @@
 //                starts the items in order as slots free); each
 //                loads its item, ranks the trues by ballot/mbcnt, writes the
 //                indices and descriptor bytes in input order and the keys,
-//                staged in LDS, as two contiguous runs.  A row that fits one
+//                staged in LDS, as two runs per wave.  A row that fits one
 //                item is read once: its T_k comes from the item itself.  A
 //                row of 2..kSibMax items is read once too (partition, row
-//                sync WAIT): its items publish their counts to one another
-//                while their keys stay in registers.
+//                sync WAIT): its items publish their counts to one another.
 #include "device.hpp"
 #include "host.hpp"
 
@@ -60,7 +61,7 @@ constexpr uint32_t kSibPolls = 64;
 // Per-item descriptor written by seg_items and completed by seg_item_bases.
 struct alignas(16) SegItem {
     int64_t lo, hi;      // valid positions [lo, hi)
-    int64_t base;        // first position of the item's 4-aligned tile
+    int64_t base;        // first position of the item's tile (4-aligned; see row_first_base)
     int64_t tbase;       // output position of the item's first true
     int64_t fbase;       // output position of the item's first false
     int32_t row;         // row k
