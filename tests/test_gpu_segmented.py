@@ -340,3 +340,19 @@ def test_any_subset_of_outputs_through_the_c_abi(mode, tune):
                 assert np.array_equal(of.cpu().numpy(), fl)
             if osp is not None:
                 assert np.array_equal(osp.cpu().numpy(), seg)
+
+
+@pytest.mark.parametrize("tune", [None, (256, 8, 64, 3), (512, 2, 64, 1)])
+def test_item_starts_on_and_off_the_cache_line(tune):
+    """A row's first item starts on the 128-byte line of its first element
+    only when that adds no item.  Rows one group short of a tile (their line
+    start would spill into a second item), rows of a whole tile behind an
+    odd offset, and rows that span several items with every start offset
+    mod 32: both choices and every offset occur, in both modes."""
+    tile = 4096 if tune is None else tune[0] * tune[1] * 4
+    parts = [np.array([3]), np.full(40, tile - 4), np.array([2]), np.full(40, tile),
+             np.full(32, 2 * tile + 5), np.arange(1, 33) * 97]
+    shape = np.concatenate(parts).astype(np.int64)
+    keys = W.int_keys(int(shape.sum()), 23)
+    for mode in (0, 1):
+        run_both(keys, shape, mode=mode, tune=tune)
